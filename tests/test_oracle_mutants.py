@@ -1,0 +1,67 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake into a copy of oracle.c (on the CPU, in a
+temporary directory), builds it, swaps it in and checks that the named pin
+tests fail.  The real oracle is restored afterwards.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle import build as obuild
+
+from . import test_oracle_kernels as K
+from . import test_oracle_solvers as S
+
+SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.c")
+
+# (name, exact source fragment, replacement, pins expected to fail)
+MUTANTS = [
+    ("cg residual sign", "r[i] = fma(-alpha, q[i], r[i]);", "r[i] = fma(alpha, q[i], r[i]);",
+     [lambda: S.test_cg_matches_dense_lu(S.inputs.poisson7_csr, (6, 5, 4))]),
+    ("cg beta inverted", "beta = rho_new / rho;", "beta = rho / rho_new;",
+     [lambda: S.test_cg_matches_dense_lu(S.inputs.poisson7_csr, (6, 5, 4))]),
+    ("cg direction update drops r", "p[i] = fma(beta, p[i], r[i]);", "p[i] = beta * p[i];",
+     [lambda: S.test_cg_finite_termination(3, 7)]),
+    ("bicgstab omega term dropped", "x[i] = fma(omega, s[i], fma(alpha, p[i], x[i]));",
+     "x[i] = fma(alpha, p[i], x[i]);",
+     [lambda: S.test_bicgstab_matches_dense_lu_upwind((5, 5, 5))]),
+    ("bicgstab beta missing omega", "double bet = an_new / (alpha_d * omega);",
+     "double bet = an_new / alpha_d;",
+     [lambda: S.test_bicgstab_finite_termination_upwind(3, 7)]),
+    ("bicgstab shadow not renormalised on restart", "rs[i] = r[i] / rnorm;\n      }\n      alpha_n = rnorm;",
+     "}\n      alpha_n = rnorm;",
+     [S.test_bicgstab_restart_paths]),
+    ("jacobi updates in place", "xb[i] = relax_row(rp, col, val, b, xa, i, dpos[i]);",
+     "xa[i] = relax_row(rp, col, val, b, xa, i, dpos[i]); xb[i] = xa[i];",
+     [lambda: S.test_jacobi_damps_slowest_mode_by_cos_pi_h(7)]),
+    ("sgs backward sweep runs forward", "for (c = ncolors - 1; c >= 0; c--) /* backward sweep */",
+     "for (c = 0; c < ncolors; c++) /* backward sweep */",
+     [lambda: S.test_redblack_sgs_mode_closed_form(2)]),
+    ("dot drops product error", "acc_add(&a, fma(x[i], y[i], -p));", "(void)0;",
+     [K.test_dot_products_split_exactly]),
+    ("dot without tie correction", "if (y == x - hi) hi = x;", "(void)x;",
+     [K.test_dot_half_way_cases]),
+    ("spmv reversed order", "for (k = rp[i]; k < rp[i + 1]; k++) acc = fma(val[k], x[col[k]], acc);",
+     "for (k = rp[i + 1] - 1; k >= rp[i]; k--) acc = fma(val[k], x[col[k]], acc);",
+     [K.test_spmv_is_an_fma_chain_in_stored_order]),
+    ("ir update unscaled", "x[i] = fma(rn, (double)d[i], x[i]);", "x[i] = x[i] + (double)d[i];",
+     [lambda: S.test_ir_cg_reaches_fp64_accuracy(S.np.float32)]),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_mutant(tmp_path, name, old, new, pins):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"fragment for '{name}' not found exactly once"
+    mut = tmp_path / "oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    so = obuild.build(source=str(mut), out=str(tmp_path / "liboracle_mut.so"))
+    prev = oracle.use_library(oracle.load(so))
+    try:
+        for pin in pins:
+            with pytest.raises(AssertionError):
+                pin()
+    finally:
+        oracle.use_library(prev)
