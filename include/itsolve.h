@@ -1,0 +1,191 @@
+/*
+ * itsolve: iterative sparse solvers for MI355X (gfx950), C ABI.
+ *
+ * Solves A x = b for a sparse A, by Jacobi, symmetric Gauss-Seidel, conjugate
+ * gradient or BiCGStab, to a relative-residual tolerance within a maximum
+ * iteration count -- the problem statement of Martinez-Ferrer, Arslan and
+ * Beltran, "Improving the performance of classical linear algebra iterative
+ * methods via hybrid parallelism" (JPDC 2023), Section 2.1.  A is given in
+ * CSR (the format of the HPCCG code the paper builds on, Section 2.2) or as
+ * a constant-coefficient 7- or 27-point stencil on a structured 3-D grid (the
+ * paper's two sparsity patterns, Section 2.1).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are HIP device memory on the current device; "host"
+ *    marks host pointers.  The caller allocates and owns all device memory;
+ *    matrix handles borrow the caller's arrays (which must outlive the
+ *    handle), and compute calls allocate no device memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is ordered on
+ *    it; calls that fill a host result return after their work completed.
+ *  - Vectors are contiguous float64 arrays of length n (the matrix's rows).
+ *  - Errors are negative its_status values and are reported before any
+ *    device work, leaving outputs untouched; its_last_error() gives a
+ *    message.  Positive values are solver outcomes, not errors.
+ *  - A handle or workspace may be used by one call at a time.
+ */
+#ifndef ITSOLVE_H
+#define ITSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct its_matrix its_matrix; /* opaque matrix handle */
+
+typedef enum {
+  ITS_OK = 0,            /* converged: ||b - A x|| (recursive) <= rtol ||b|| */
+  ITS_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate */
+  ITS_BREAKDOWN = 2,     /* a solver denominator vanished or became non-finite */
+  ITS_E_INVALID = -1,    /* invalid argument (null, size, NaN/Inf in b, ...) */
+  ITS_E_HIP = -2,        /* a HIP runtime call failed */
+  ITS_E_WORKSPACE = -3,  /* workspace missing or too small */
+  ITS_E_UNSUPPORTED = -4 /* valid request this build does not support */
+} its_status;
+
+typedef enum { ITS_JACOBI = 0, ITS_SGS = 1, ITS_CG = 2, ITS_BICGSTAB = 3 } its_method;
+typedef enum { ITS_F64 = 0, ITS_F32 = 1, ITS_F16 = 2 } its_dtype;
+typedef enum { ITS_RESTART_COSINE = 0, ITS_RESTART_PAPER = 1 } its_restart_mode;
+
+/* Solver options.  Use its_default_options() and change fields. */
+typedef struct {
+  int32_t method;       /* its_method */
+  int32_t restart_mode; /* BiCGStab restart test (Algorithm 2; see its_solve) */
+  double rtol;          /* relative residual tolerance, >= 0 */
+  int64_t max_iter;     /* iteration cap (IR: cap on total inner iterations) */
+  double restart_tol;   /* BiCGStab restart threshold (paper: 1e-5) */
+  int32_t check_every;  /* host polls the device status every this many
+                           iterations; 0 = automatic */
+  int32_t inner_dtype;  /* CG only.  ITS_F64: plain FP64 CG.  ITS_F32/ITS_F16:
+                           mixed-precision iterative refinement whose inner CG
+                           uses the matrix's low-precision values of that type
+                           (its_csr_set_lowp) and FP32 vectors */
+  double inner_rtol;    /* IR: relative tolerance of each inner solve */
+  int64_t max_outer;    /* IR: cap on refinement steps */
+  int32_t profile;      /* 1: time every kernel launch with HIP events and
+                           report per-class totals in its_result */
+  int32_t reserved;
+} its_options;
+
+#define ITS_MAX_KERNEL_CLASSES 8
+
+typedef struct {
+  int32_t status;       /* its_status */
+  int32_t restarts;     /* BiCGStab restarts performed */
+  int64_t iters;        /* iterations (IR: refinement steps) */
+  int64_t inner_iters;  /* IR: total inner CG iterations */
+  double rel_res;       /* recursive ||r_k|| / ||b|| at exit */
+  double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit */
+  /* profile != 0 only: summed duration and launch count per kernel class.
+     CG: 0 = SpMV+dot pass, 1 = update+dot pass.  BiCGStab: 0 = A p pass,
+     1 = A s pass, 2 = update pass.  Jacobi: 0 = sweep.  SGS: 0 = colour
+     half-sweeps, 1 = residual.  IR: 0/1 = inner passes as CG, 2 = outer
+     residual, 3 = outer scaling and update. */
+  double kernel_ms[ITS_MAX_KERNEL_CLASSES];
+  int64_t kernel_launches[ITS_MAX_KERNEL_CLASSES];
+} its_result;
+
+/* Defaults: CG, rtol 1e-8, max_iter 10000, restart COSINE with 1e-5,
+   inner_dtype F64, inner_rtol 1e-4, max_outer 30. */
+void its_default_options(its_options *opts /* host, out */);
+
+/* ---------------------------------------------------------------- matrices */
+
+/* CSR matrix (Section 2.2).  row_ptr: n+1 int32 (row_ptr[0] = 0,
+   nondecreasing, row_ptr[n] = nnz); col: nnz int32 in [0, n); val: nnz
+   float64.  Rows are applied in stored order (store columns ascending).
+   All three are device pointers, borrowed.  Requires nnz < 2^31.
+   Structure is not validated here (use its_csr_validate). */
+its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                          const double *val, its_matrix **out /* host, out */);
+
+/* Checks a CSR matrix on the device: row_ptr monotone and in range, columns
+   in range and strictly ascending within each row.  If need_diag, every row
+   must also hold a nonzero diagonal entry (Jacobi, Gauss-Seidel).
+   Returns ITS_OK or ITS_E_INVALID. */
+its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream);
+
+/* Attaches low-precision copies of the CSR values (same structure) for the
+   mixed-precision CG: dtype ITS_F32 (float) or ITS_F16 (IEEE half).  Device
+   pointer, borrowed.  One array per dtype may be attached. */
+its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
+
+/* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 2.4:
+   colours, red-black without rotation).  color: n uint8 (device) with values
+   < ncolors; each colour must be an independent set (no row couples to a
+   row of its own colour) -- checked here, ITS_E_INVALID otherwise.  The
+   handle keeps per-colour row lists in device memory it allocates and frees
+   in its_matrix_destroy. */
+its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolors, void *stream);
+
+/* Matrix-free constant-coefficient stencil on an nx*ny*nz grid, rows
+   numbered i + nx*(j + ny*k), neighbours outside the grid omitted
+   (Dirichlet).  npts = 7 or 27.  coef (host, copied): one value per offset
+   in ascending column order -- 7-point: (k-1, j-1, i-1, centre, i+1, j+1,
+   k+1); 27-point: dk outer, dj, di inner, each -1..1.  Gauss-Seidel uses the
+   red-black colouring (i+j+k) mod 2 for 7 points and the 8 colours
+   (i mod 2) + 2 (j mod 2) + 4 (k mod 2) for 27 points.  Requires
+   nx*ny*nz < 2^31. */
+its_status its_stencil_create(int32_t nx, int32_t ny, int32_t nz, int32_t npts,
+                              const double *coef, its_matrix **out /* host, out */);
+
+its_status its_matrix_destroy(its_matrix *A);
+int64_t its_matrix_rows(const its_matrix *A);
+
+/* ----------------------------------------------------------------- kernels */
+
+/* y = A x, each row a fused multiply-add chain over its entries in stored
+   (ascending column) order starting from +0.  x, y: device, length n, not
+   aliased. */
+its_status its_spmv(const its_matrix *A, const double *x, double *y, void *stream);
+
+/* Dot product (the paper's scalar products): the sum of x_i*y_i computed
+   with error-free transformations (double-double accumulation) and rounded
+   once.  Its error is at most half an ulp of the result plus about
+   n * 2^-104 * sum|x_i y_i|, so it is the correctly rounded value unless the
+   sum cancels to near a rounding boundary (r.r never does).  result: host.
+   workspace: device, at least its_dot_workspace_size(n) bytes. */
+size_t its_dot_workspace_size(int64_t n);
+its_status its_dot(int64_t n, const double *x, const double *y, double *result, void *workspace,
+                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------- solve */
+
+/* Device workspace in bytes needed by its_solve for this matrix/options. */
+its_status its_workspace_size(const its_matrix *A, const its_options *opts, size_t *bytes);
+
+/* Solves A x = b.  b: device, n.  x: device, n, in = x0, out = solution.
+   Stops when ||r_k||_2 <= rtol ||b||_2 (the paper's test is absolute;
+   Algorithms 1-2) or after max_iter iterations.  b = 0 returns x = 0.
+   Methods (Section 2.1):
+     ITS_JACOBI   x_{k+1} = D^{-1}(b - (A - D) x_k), undamped;
+     ITS_SGS      symmetric Gauss-Seidel: colours forward then backward;
+     ITS_CG       classical CG (Hestenes-Stiefel), or mixed-precision IR;
+     ITS_BICGSTAB BiCGStab with the arithmetic of Algorithm 2 and its
+                  restart: COSINE restarts when |r.r'| < restart_tol ||r||,
+                  PAPER when sqrt(|r.r'|) < restart_tol.
+   Returns ITS_OK / ITS_NOT_CONVERGED / ITS_BREAKDOWN with res filled and x
+   holding the returned iterate, or a negative error with x untouched.
+   res: host, out. */
+its_status its_solve(const its_matrix *A, const its_options *opts, const double *b, double *x,
+                     void *workspace, size_t ws_bytes, void *stream, its_result *res);
+
+/* --------------------------------------------------------------- utilities */
+
+/* dst[i] = src[i] rounded to nearest-even in dtype (ITS_F32 or ITS_F16):
+   builds low-precision matrix values for its_csr_set_lowp. */
+its_status its_cast_values(const double *src, void *dst, int32_t dtype, int64_t count, void *stream);
+
+/* dst = src, a streaming copy of n float64: the bandwidth probe against
+   which HBM traffic counters are calibrated. */
+its_status its_stream_copy(const double *src, double *dst, int64_t n, void *stream);
+
+const char *its_status_string(int32_t status);
+const char *its_last_error(void); /* message of this thread's last error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ITSOLVE_H */

@@ -245,7 +245,7 @@ int orc_jacobi(int64_t n, const int64_t *rp, const int32_t *col, const double *v
       res->status = ORC_OK;
       break;
     }
-    if (rr != rr) {
+    if (!isfinite(rr)) {
       res->status = ORC_BREAKDOWN;
       break;
     }
@@ -317,7 +317,7 @@ int orc_sgs(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
       res->status = ORC_OK;
       break;
     }
-    if (rr != rr) {
+    if (!isfinite(rr)) {
       res->status = ORC_BREAKDOWN;
       break;
     }
@@ -368,7 +368,7 @@ int orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
       res->status = ORC_OK;
       break;
     }
-    if (rho != rho) {
+    if (!isfinite(rho)) {
       res->status = ORC_BREAKDOWN;
       break;
     }
@@ -460,7 +460,7 @@ int orc_bicgstab(int64_t n, const int64_t *rp, const int32_t *col, const double 
       res->status = ORC_OK;
       break;
     }
-    if (beta != beta) {
+    if (!isfinite(beta)) {
       res->status = ORC_BREAKDOWN;
       break;
     }
@@ -568,7 +568,7 @@ int orc_ir_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *va
       res->status = ORC_OK;
       break;
     }
-    if (rho != rho) {
+    if (!isfinite(rho)) {
       res->status = ORC_BREAKDOWN;
       break;
     }

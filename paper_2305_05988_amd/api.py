@@ -1,0 +1,215 @@
+"""Python binding of the C ABI: torch tensors in, torch tensors out.
+
+Argument marshalling only -- device memory and streams come from torch, and
+every step of every computation runs in libitsolve.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_METHODS = {"jacobi": L.ITS_JACOBI, "sgs": L.ITS_SGS, "gs": L.ITS_SGS, "cg": L.ITS_CG,
+            "bicgstab": L.ITS_BICGSTAB}
+_DTYPES = {"f64": L.ITS_F64, "f32": L.ITS_F32, "f16": L.ITS_F16}
+_RESTART = {"cosine": L.ITS_RESTART_COSINE, "paper": L.ITS_RESTART_PAPER}
+_STATUS = {L.ITS_OK: "ok", L.ITS_NOT_CONVERGED: "not_converged", L.ITS_BREAKDOWN: "breakdown"}
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(device=None) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _vec(t, n, name, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} elements")
+    return t
+
+
+class _Matrix:
+    _h = None
+
+    def __del__(self):
+        if self._h is not None and L._lib is not None:
+            L._lib.its_matrix_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+
+class CSRMatrix(_Matrix):
+    """CSR matrix on the GPU: int32 row_ptr (n+1), int32 col, float64 val.
+    The handle borrows the tensors; this object keeps them alive."""
+
+    def __init__(self, row_ptr, col, val, val32=None, val16=None, validate=True):
+        self.n = row_ptr.numel() - 1
+        self.nnz = col.numel()
+        _vec(row_ptr, self.n + 1, "row_ptr", torch.int32)
+        _vec(col, self.nnz, "col", torch.int32)
+        _vec(val, self.nnz, "val")
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        h = C.c_void_p()
+        L.check(L.lib().its_csr_create(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                       C.byref(h)), "its_csr_create")
+        self._h = h
+        self.val32 = self.val16 = None
+        if validate:
+            L.check(L.lib().its_csr_validate(self._h, 0, _stream()), "its_csr_validate")
+        if val32 is not None:
+            self.set_lowp(val32)
+        if val16 is not None:
+            self.set_lowp(val16)
+        self.colors = None
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col, val, device="cuda", lowp=(), validate=True):
+        """Uploads host CSR arrays (row_ptr narrowed to int32) and, for each
+        dtype name in ``lowp`` ("f32", "f16"), a low-precision copy of the
+        values made by the library's cast kernel."""
+        rp = np.asarray(row_ptr)
+        if rp[-1] >= 2 ** 31:
+            raise ValueError("nnz must be below 2^31")
+        t_rp = torch.from_numpy(np.ascontiguousarray(rp, dtype=np.int32)).to(device)
+        t_col = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
+        t_val = torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(device)
+        A = cls(t_rp, t_col, t_val, validate=validate)
+        for d in lowp:
+            A.set_lowp(cast_values(t_val, d))
+        return A
+
+    def set_lowp(self, v):
+        if v.dtype == torch.float32:
+            dt = L.ITS_F32
+            self.val32 = v
+        elif v.dtype == torch.float16:
+            dt = L.ITS_F16
+            self.val16 = v
+        else:
+            raise ValueError("low-precision values must be float32 or float16")
+        _vec(v, self.nnz, "val_lo", v.dtype)
+        L.check(L.lib().its_csr_set_lowp(self._h, _ptr(v), dt), "its_csr_set_lowp")
+
+    def set_colors(self, color, ncolors):
+        """Point colouring for Gauss-Seidel: uint8 tensor of n colours."""
+        if not isinstance(color, torch.Tensor):
+            color = torch.from_numpy(np.ascontiguousarray(color, dtype=np.uint8)).cuda()
+        _vec(color, self.n, "color", torch.uint8)
+        L.check(L.lib().its_csr_set_colors(self._h, _ptr(color), int(ncolors), _stream()),
+                "its_csr_set_colors")
+        self.colors = color
+
+
+class StencilMatrix(_Matrix):
+    """Matrix-free constant-coefficient 7- or 27-point stencil on nx*ny*nz."""
+
+    def __init__(self, nx, ny, nz, coef):
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        if coef.size not in (7, 27):
+            raise ValueError("coef must hold 7 or 27 values")
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.coef = coef
+        h = C.c_void_p()
+        L.check(L.lib().its_stencil_create(self.nx, self.ny, self.nz, coef.size,
+                                           coef.ctypes.data_as(C.c_void_p), C.byref(h)),
+                "its_stencil_create")
+        self._h = h
+
+
+def spmv(A, x, y=None):
+    x = _vec(x, A.n, "x")
+    y = torch.empty_like(x) if y is None else _vec(y, A.n, "y")
+    L.check(L.lib().its_spmv(A.handle, _ptr(x), _ptr(y), _stream()), "its_spmv")
+    return y
+
+
+def dot(x, y) -> float:
+    n = x.numel()
+    _vec(x, n, "x")
+    _vec(y, n, "y")
+    ws = torch.empty(L.lib().its_dot_workspace_size(n), dtype=torch.uint8, device=x.device)
+    out = C.c_double()
+    L.check(L.lib().its_dot(n, _ptr(x), _ptr(y), C.byref(out), _ptr(ws), ws.numel(), _stream()),
+            "its_dot")
+    return out.value
+
+
+def cast_values(v, dtype: str):
+    out = torch.empty(v.numel(), device=v.device,
+                      dtype={"f32": torch.float32, "f16": torch.float16}[dtype])
+    L.check(L.lib().its_cast_values(_ptr(v), _ptr(out), _DTYPES[dtype], v.numel(), _stream()),
+            "its_cast_values")
+    return out
+
+
+def stream_copy(src, dst):
+    L.check(L.lib().its_stream_copy(_ptr(src), _ptr(dst), src.numel(), _stream()),
+            "its_stream_copy")
+    return dst
+
+
+@dataclass
+class SolveInfo:
+    status: str
+    code: int
+    iters: int
+    inner_iters: int
+    restarts: int
+    rel_res: float
+    true_rel_res: float
+    kernel_ms: list = field(default_factory=list)
+    kernel_launches: list = field(default_factory=list)
+
+
+def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mode="cosine",
+            inner_dtype="f64", inner_rtol=1e-4, max_outer=30, check_every=0, profile=False):
+    o = L.Options()
+    L.lib().its_default_options(C.byref(o))
+    o.method = _METHODS[method]
+    o.rtol = rtol
+    o.max_iter = max_iter
+    o.restart_tol = restart_tol
+    o.restart_mode = _RESTART[restart_mode]
+    o.inner_dtype = _DTYPES[inner_dtype]
+    o.inner_rtol = inner_rtol
+    o.max_outer = max_outer
+    o.check_every = check_every
+    o.profile = 1 if profile else 0
+    return o
+
+
+def workspace_bytes(A, **opts) -> int:
+    o = options(**opts)
+    nb = C.c_size_t()
+    L.check(L.lib().its_workspace_size(A.handle, C.byref(o), C.byref(nb)), "its_workspace_size")
+    return nb.value
+
+
+def solve(A, b, x0=None, workspace=None, **opts):
+    """Solves A x = b.  Returns (x, SolveInfo); raises ItsError on invalid
+    arguments.  x0 (optional) is copied; pass ``x=`` semantics via x0."""
+    b = _vec(b, A.n, "b")
+    x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    o = options(**opts)
+    nb = C.c_size_t()
+    L.check(L.lib().its_workspace_size(A.handle, C.byref(o), C.byref(nb)), "its_workspace_size")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=b.device)
+    r = L.Result()
+    st = L.check(L.lib().its_solve(A.handle, C.byref(o), _ptr(b), _ptr(x), _ptr(workspace),
+                                   workspace.numel(), _stream(), C.byref(r)), "its_solve")
+    info = SolveInfo(_STATUS.get(st, str(st)), st, r.iters, r.inner_iters, r.restarts,
+                     r.rel_res, r.true_rel_res, list(r.kernel_ms), list(r.kernel_launches))
+    return x, info

@@ -1,0 +1,202 @@
+// Device building blocks shared by every kernel of the library: error-free
+// floating-point transformations, the deterministic two-level dot-product
+// reduction, the XCD-aware tile schedule and the device-resident solver
+// state.  gfx950 (CDNA4): 64-wide wavefronts, 256 CUs in 8 XCDs.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace its {
+
+constexpr int kBlock = 256;             // threads per block: 4 wave64
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxGrid = 2048;          // cap on blocks of the streaming kernels
+constexpr int kMaxDots = 2;             // dot products reduced per kernel
+constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dealt round-robin
+
+// Solver status flags kept on the device.
+enum : int32_t { kRunning = 0, kConverged = 1, kMaxIter = 2, kBreakdown = 3 };
+
+// Device-resident scalars of one solve.  Kernels read them at entry and the
+// last block of a reducing kernel updates them; the host reads a snapshot
+// only when it polls.
+struct alignas(256) State {
+  int32_t flag;       // kRunning / kConverged / kMaxIter / kBreakdown
+  int32_t restart;    // BiCGStab: the next A p pass starts from a restart
+  int64_t k;          // completed iterations
+  int32_t restarts;   // BiCGStab restarts so far
+  int32_t pad;
+  uint32_t counter[8];// arrival counters of the last-block reductions
+  double rho;         // r.r of the current iterate (CG); beta = r.r (BiCGStab)
+  double alpha;       // step length
+  double beta;        // CG: direction coefficient; BiCGStab: p coefficient
+  double omega;       // BiCGStab stabilising step
+  double alpha_n;     // BiCGStab r.r'
+  double alpha_d;     // BiCGStab (A p).r'
+  double ts, tt;      // BiCGStab (A s).s and (A s).(A s)
+  double dot[4];      // scratch results (dot products, residual norms)
+};
+
+// ---------------------------------------------------------------- floating point
+// Written-out roundings: the library is compiled with -ffp-contract=off, so
+// a*b+c is two roundings and fma() is one, exactly as written.
+
+struct DD {  // unevaluated sum hi + lo, |lo| <= ulp(hi)/2 when normalised
+  double hi, lo;
+};
+
+__device__ __forceinline__ DD two_sum(double a, double b) {
+  const double s = a + b;
+  const double bp = s - a;
+  const double e = (a - (s - bp)) + (b - bp);
+  return {s, e};
+}
+
+__device__ __forceinline__ DD fast_two_sum(double a, double b) {  // |a| >= |b|
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+
+// Accurate double-double addition (error ~ 2^-104 relative to |a|+|b|).
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+  DD s = two_sum(a.hi, b.hi);
+  const DD t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+// Per-thread compensated dot accumulator (Ogita-Rump-Oishi Dot2): the
+// product error comes from fma, the sum error from two_sum; both are summed
+// into c.  A float*float product is exact in double, so its error term is 0.
+struct Dot2 {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x, double y) {
+    const double p = x * y;
+    const double e = fma(x, y, -p);
+    const DD t = two_sum(s, p);
+    s = t.hi;
+    c += t.lo + e;
+  }
+  __device__ __forceinline__ DD get() const { return two_sum(s, c); }
+};
+
+__device__ __forceinline__ double dd_round(DD v) { return v.hi + v.lo; }
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+
+// --------------------------------------------------------------- tile schedule
+// Rows are processed in tiles of kBlock rows, one row per thread.  With at
+// least 64 blocks (a multiple of 8) the tiles are cut into 8 contiguous
+// chunks and chunk x is served by the blocks that the hardware places on XCD
+// x (block ids congruent to x mod 8), so the neighbour rows a stencil-like
+// matrix gathers (+-1, +-nx, +-nx*ny) stay in one XCD's L2.
+struct Sched {
+  int64_t begin, end, stride;
+};
+
+__device__ __forceinline__ Sched my_tiles(int64_t ntiles) {
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  if (G < 64 || (G % kXcds) != 0) return {b, ntiles, G};
+  const int x = b % kXcds, slot = b / kXcds, per = G / kXcds;
+  const int64_t lo = ntiles * x / kXcds, hi = ntiles * (x + 1) / kXcds;
+  return {lo + slot, hi, per};
+}
+
+template <class Body>
+__device__ __forceinline__ void for_rows(int32_t n, Body &&body) {
+  const int64_t ntiles = (int64_t(n) + kBlock - 1) / kBlock;
+  const Sched s = my_tiles(ntiles);
+  for (int64_t t = s.begin; t < s.end; t += s.stride) {
+    const int64_t i = t * kBlock + threadIdx.x;
+    if (i < n) body(int32_t(i));
+  }
+}
+
+// --------------------------------------------------------------- reductions
+
+__device__ __forceinline__ DD wave_reduce(DD v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    DD o;
+    o.hi = __shfl_xor(v.hi, off);
+    o.lo = __shfl_xor(v.lo, off);
+    v = dd_add(v, o);
+  }
+  return v;
+}
+
+// Reduces ND per-thread values over the block; the result is valid in
+// thread 0.  Fixed order: butterfly within each wave, then waves 0..3.
+template <int ND>
+__device__ __forceinline__ void block_reduce(DD (&v)[ND]) {
+  __shared__ DD sm[ND][kWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) v[d] = wave_reduce(v[d]);
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sm[d][w] = v[d];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      DD t = sm[d][0];
+      for (int j = 1; j < kWaves; ++j) t = dd_add(t, sm[d][j]);
+      v[d] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Grid-wide reduction without a second launch: every block stores its
+// partial, and the block that arrives last (arrival counter) sums all G
+// partials in block order -- a fixed order, so the result does not depend on
+// scheduling -- and returns true in thread 0 with the totals in v.  The
+// counter is re-armed by that block.  Every block of the grid must call this.
+template <int ND>
+__device__ __forceinline__ bool grid_reduce(DD (&v)[ND], DD *partials, uint32_t *counter) {
+  __shared__ int s_last;
+  const int G = gridDim.x;
+  block_reduce<ND>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) partials[d * kMaxGrid + blockIdx.x] = v[d];
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
+    s_last = (prev == uint32_t(G - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    DD t = {0.0, 0.0};
+    for (int j = threadIdx.x; j < G; j += kBlock) t = dd_add(t, partials[d * kMaxGrid + j]);
+    v[d] = t;
+  }
+  block_reduce<ND>(v);
+  if (threadIdx.x == 0) *counter = 0u;
+  return threadIdx.x == 0;
+}
+
+// ---------------------------------------------------------------- launch size
+
+inline int grid_for(int64_t n) {
+  int64_t tiles = (n + kBlock - 1) / kBlock;
+  if (tiles < 1) tiles = 1;
+  int g = int(tiles < kMaxGrid ? tiles : kMaxGrid);
+  if (g >= 64) g -= g % kXcds;
+  return g;
+}
+
+}  // namespace its

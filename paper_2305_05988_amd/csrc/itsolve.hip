@@ -1,0 +1,893 @@
+// The C ABI of include/itsolve.h: argument validation, matrix handles,
+// workspace layout and the host drivers of each method.  A driver launches
+// the fused passes of m iterations back to back (m = check_every) and then
+// reads the device State once; scalars never leave the device in between.
+#include "../../include/itsolve.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace its;
+
+enum MatKind { kCsr = 0, kSten7 = 1, kSten27 = 2 };
+
+struct its_matrix {
+  int kind = kCsr;
+  int64_t n = 0, nnz = 0;
+  const int32_t *rp = nullptr, *col = nullptr;
+  const double *val = nullptr;
+  const float *val32 = nullptr;
+  const __half *val16 = nullptr;
+  int32_t nx = 0, ny = 0, nz = 0;
+  double coef[27] = {};
+  // Gauss-Seidel colouring (CSR): rows grouped by colour, owned
+  int32_t ncolors = 0;
+  int32_t *color_rows = nullptr;
+  std::vector<int32_t> color_off;
+  int diag_state = 0;  // CSR: 0 unchecked, 1 every row has a nonzero diagonal, -1 not
+  State *host_state = nullptr;  // pinned snapshot buffer for polling
+};
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static its_status fail(its_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ITS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------- profiling
+
+namespace {
+
+struct Prof {
+  bool on = false;
+  its_result *res = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+  size_t used = 0;
+  ~Prof() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  void begin(int c, hipStream_t s) {
+    if (!on) return;
+    while (ev.size() < used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      ev.push_back(e);
+    }
+    (void)hipEventRecord(ev[used], s);
+    cls.push_back(c);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(ev[used + 1], s);
+    used += 2;
+  }
+  void flush() {  // after a stream synchronisation
+    if (!on) return;
+    for (size_t p = 0; p < cls.size(); ++p) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]) == hipSuccess) {
+        res->kernel_ms[cls[p]] += ms;
+        res->kernel_launches[cls[p]] += 1;
+      }
+    }
+    cls.clear();
+    used = 0;
+  }
+};
+
+struct Run {
+  hipStream_t s;
+  Prof prof;
+  template <class K, class... Args>
+  hipError_t launch(int cls, K kernel, int grid, Args... args) {
+    prof.begin(cls, s);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, args...);
+    prof.end(s);
+    return hipGetLastError();
+  }
+};
+
+#define LAUNCH(run, cls, kernel, grid, ...)                                                   \
+  do {                                                                                        \
+    hipError_t e_ = (run).launch(cls, kernel, grid, __VA_ARGS__);                             \
+    if (e_ != hipSuccess) return fail(ITS_E_HIP, std::string("launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------ workspace
+// [State main][State inner][partials: kMaxDots*kMaxGrid DD][vectors...],
+// every section 256-byte aligned.
+constexpr size_t kAlign = 256;
+inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t state = 0, state2 = 0, partials = 0, vec = 0, total = 0;
+  int nvec64 = 0, nvec32 = 0;
+};
+
+Layout layout_for(int64_t n, int method, int inner_dtype) {
+  Layout L;
+  L.state = 0;
+  L.state2 = up(sizeof(State));
+  L.partials = L.state2 + up(sizeof(State));
+  L.vec = L.partials + up(sizeof(DD) * kMaxDots * kMaxGrid);
+  switch (method) {
+    case ITS_JACOBI: L.nvec64 = 1; break;
+    case ITS_SGS: L.nvec64 = 0; break;
+    case ITS_CG: L.nvec64 = (inner_dtype == ITS_F64) ? 3 : 1; L.nvec32 = (inner_dtype == ITS_F64) ? 0 : 4; break;
+    case ITS_BICGSTAB: L.nvec64 = 7; break;
+    default: break;
+  }
+  L.total = L.vec + size_t(L.nvec64) * up(size_t(n) * 8) + size_t(L.nvec32) * up(size_t(n) * 4);
+  return L;
+}
+
+struct WS {
+  State *st, *st2;
+  DD *partials;
+  char *vec;
+  size_t n;
+  double *v64(int i) const { return reinterpret_cast<double *>(vec + size_t(i) * up(n * 8)); }
+  float *v32(int nvec64, int i) const {
+    return reinterpret_cast<float *>(vec + size_t(nvec64) * up(n * 8) + size_t(i) * up(n * 4));
+  }
+};
+
+WS carve(void *ws, const Layout &L, int64_t n) {
+  char *b = static_cast<char *>(ws);
+  return {reinterpret_cast<State *>(b + L.state), reinterpret_cast<State *>(b + L.state2),
+          reinterpret_cast<DD *>(b + L.partials), b + L.vec, size_t(n)};
+}
+
+// ------------------------------------------------------------ operators
+
+template <class F>
+its_status with_op64(const its_matrix *A, F &&f) {
+  switch (A->kind) {
+    case kCsr: return f(CsrOp<double, double>{A->rp, A->col, A->val, int32_t(A->n)});
+    case kSten7: {
+      StencilOp<7, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
+      for (int o = 0; o < 7; ++o) op.c[o] = A->coef[o];
+      return f(op);
+    }
+    default: {
+      StencilOp<27, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
+      for (int o = 0; o < 27; ++o) op.c[o] = A->coef[o];
+      return f(op);
+    }
+  }
+}
+
+template <class F>
+its_status with_op32(const its_matrix *A, int dtype, F &&f) {
+  switch (A->kind) {
+    case kCsr:
+      if (dtype == ITS_F32) return f(CsrOp<float, float>{A->rp, A->col, A->val32, int32_t(A->n)});
+      return f(CsrOp<__half, float>{A->rp, A->col, A->val16, int32_t(A->n)});
+    case kSten7: {
+      StencilOp<7, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
+      for (int o = 0; o < 7; ++o)
+        op.c[o] = dtype == ITS_F32 ? float(A->coef[o]) : float(static_cast<_Float16>(A->coef[o]));
+      return f(op);
+    }
+    default: {
+      StencilOp<27, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
+      for (int o = 0; o < 27; ++o)
+        op.c[o] = dtype == ITS_F32 ? float(A->coef[o]) : float(static_cast<_Float16>(A->coef[o]));
+      return f(op);
+    }
+  }
+}
+
+// ------------------------------------------------------------- polling
+
+its_status poll(Run &run, const State *dev, State *host) {
+  HIP_TRY(hipMemcpyAsync(host, dev, sizeof(State), hipMemcpyDeviceToHost, run.s));
+  HIP_TRY(hipStreamSynchronize(run.s));
+  run.prof.flush();
+  return ITS_OK;
+}
+
+its_status flag_to_status(int32_t f) {
+  switch (f) {
+    case kConverged: return ITS_OK;
+    case kMaxIter: return ITS_NOT_CONVERGED;
+    default: return ITS_BREAKDOWN;
+  }
+}
+
+int batch_size(const its_options *o, int64_t n) {
+  if (o->check_every > 0) return o->check_every;
+  return n >= (int64_t(1) << 20) ? 8 : 32;
+}
+
+// Runs iterations j = j0, j0+1, ... until the device flag leaves kRunning or
+// max_iter iterations were launched; `step(j)` launches iteration j.
+template <class Step>
+its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, int m, Step &&step) {
+  int64_t j = 0;
+  for (;;) {
+    const int64_t todo = std::min<int64_t>(m, max_iter - j);
+    for (int64_t t = 0; t < todo; ++t, ++j) {
+      its_status st = step(j);
+      if (st != ITS_OK) return st;
+    }
+    its_status st = poll(run, dev, host);
+    if (st != ITS_OK) return st;
+    if (host->flag != kRunning) return ITS_OK;
+    if (j >= max_iter) return fail(ITS_E_HIP, "device state still running after max_iter");
+  }
+}
+
+// Common prologue: zero the States, b.b, r0 = b - A x0 (stored in r if
+// non-null) and r0.r0.  Returns bb and rr0 through `host`.
+its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b, const double *x,
+                    double *r, State *host, double &bb, double &rr) {
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  LAUNCH(run, 7, k_reset_state, 1, w.st, 2);
+  LAUNCH(run, 7, k_dot, G, n, b, b, w.st, w.partials, 0, 0);
+  its_status s = with_op64(A, [&](auto op) -> its_status {
+    LAUNCH(run, 7, k_residual<decltype(op)>, G, op, b, x, r, w.st, w.partials, 1, 1);
+    return ITS_OK;
+  });
+  if (s != ITS_OK) return s;
+  s = poll(run, w.st, host);
+  if (s != ITS_OK) return s;
+  bb = host->dot[0];
+  rr = host->dot[1];
+  return ITS_OK;
+}
+
+double threshold2(double rtol, double bb) {
+  const double t = rtol * std::sqrt(bb);
+  return t * t;
+}
+
+its_status true_residual(Run &run, const its_matrix *A, const WS &w, const double *b,
+                         const double *x, State *host, double bb, its_result *res) {
+  const int G = grid_for(A->n);
+  its_status s = with_op64(A, [&](auto op) -> its_status {
+    LAUNCH(run, 7, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, w.st2, w.partials, 5, 2);
+    return ITS_OK;
+  });
+  if (s != ITS_OK) return s;
+  s = poll(run, w.st2, host);
+  if (s != ITS_OK) return s;
+  res->true_rel_res = std::sqrt(host->dot[2]) / std::sqrt(bb);
+  return ITS_OK;
+}
+
+// ------------------------------------------------------------------- CG
+
+its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const double *b, double *x,
+                    const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  double *r = w.v64(0), *p = w.v64(1), *q = w.v64(2);
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  int32_t flag = kRunning;
+  if (rr <= thr2) flag = kConverged;
+  else if (!std::isfinite(rr)) flag = kBreakdown;
+  else if (o->max_iter <= 0) flag = kMaxIter;
+  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  if (flag == kRunning) {
+    s = with_op64(A, [&](auto op) -> its_status {
+      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
+        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double *)r, (const double *)p, q, w.st, w.partials);
+        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, r, p, (const double *)q, w.st, w.partials, thr2, o->max_iter);
+        return ITS_OK;
+      });
+    });
+    if (s != ITS_OK) return s;
+  } else {
+    s = poll(run, w.st, h);
+    if (s != ITS_OK) return s;
+  }
+  res->status = flag_to_status(h->flag);
+  res->iters = h->k;
+  res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  return true_residual(run, A, w, b, x, h, bb, res);
+}
+
+// ------------------------------------------- mixed-precision refinement CG
+
+its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const double *b, double *x,
+                    const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  const int dt = o->inner_dtype;
+  if (A->kind == kCsr && ((dt == ITS_F32 && !A->val32) || (dt == ITS_F16 && !A->val16)))
+    return fail(ITS_E_INVALID, "mixed precision needs its_csr_set_lowp values of that dtype");
+  double *r = w.v64(0);
+  float *rh = w.v32(1, 0), *p = w.v32(1, 1), *q = w.v32(1, 2), *d = w.v32(1, 3);
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  int64_t inner_total = 0;
+  int64_t outer = 0;
+  for (;; ++outer) {
+    if (outer > 0) {  // r = b - A x of the refined iterate
+      s = with_op64(A, [&](auto op) -> its_status {
+        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, w.st, w.partials, 1, 1);
+        return ITS_OK;
+      });
+      if (s != ITS_OK) return s;
+      s = poll(run, w.st, h);
+      if (s != ITS_OK) return s;
+      rr = h->dot[1];
+    }
+    if (rr <= thr2) { res->status = ITS_OK; break; }
+    if (!std::isfinite(rr)) { res->status = ITS_BREAKDOWN; break; }
+    if (outer == o->max_outer || inner_total >= o->max_iter) { res->status = ITS_NOT_CONVERGED; break; }
+    const double rn = std::sqrt(rr);
+    LAUNCH(run, 3, k_ir_scale, G, n, (const double *)r, rh, d, w.st2, w.partials, rn);
+    s = poll(run, w.st2, h);
+    if (s != ITS_OK) return s;
+    const double rho_i = h->dot[1];
+    const double ithr2 = threshold2(o->inner_rtol, rho_i);
+    const int64_t budget = o->max_iter - inner_total;
+    if (!(rho_i <= ithr2)) {
+      LAUNCH(run, 7, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
+      s = with_op32(A, dt, [&](auto op) -> its_status {
+        return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
+          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float *)rh, (const float *)p, q, w.st2, w.partials);
+          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rh, p, (const float *)q, w.st2, w.partials, ithr2, budget);
+          return ITS_OK;
+        });
+      });
+      if (s != ITS_OK) return s;
+      inner_total += h->k;
+      if (h->flag == kBreakdown) { res->status = ITS_BREAKDOWN; break; }
+    }
+    LAUNCH(run, 3, k_ir_update, G, n, x, (const float *)d, rn);
+  }
+  res->iters = outer;
+  res->inner_iters = inner_total;
+  res->rel_res = std::sqrt(rr) / std::sqrt(bb);
+  res->true_rel_res = res->rel_res;
+  HIP_TRY(hipStreamSynchronize(run.s));
+  run.prof.flush();
+  return ITS_OK;
+}
+
+// ------------------------------------------------------------- BiCGStab
+
+its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, const double *b,
+                          double *x, const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  double *r = w.v64(0), *rs = w.v64(1), *P[2] = {w.v64(2), w.v64(3)}, *V[2] = {w.v64(4), w.v64(5)},
+         *t = w.v64(6);
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  int32_t flag = kRunning;
+  if (rr <= thr2) flag = kConverged;
+  else if (!std::isfinite(rr)) flag = kBreakdown;
+  else if (o->max_iter <= 0) flag = kMaxIter;
+  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  if (flag == kRunning) {
+    LAUNCH(run, 7, k_bicg_init, G, n, (const double *)r, rs, w.st, w.partials, std::sqrt(rr));
+    const double rt2 = o->restart_tol * o->restart_tol;
+    const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
+    s = with_op64(A, [&](auto op) -> its_status {
+      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
+        const int a = int(j & 1), c = a ^ 1;
+        LAUNCH(run, 0, k_bicg_a<decltype(op)>, G, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], w.st, w.partials);
+        LAUNCH(run, 1, k_bicg_b<decltype(op)>, G, op, (const double *)r, (const double *)V[c], t, w.st, w.partials);
+        LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, w.st, w.partials, thr2, o->max_iter, rt2, paper);
+        return ITS_OK;
+      });
+    });
+    if (s != ITS_OK) return s;
+  } else {
+    s = poll(run, w.st, h);
+    if (s != ITS_OK) return s;
+  }
+  res->status = flag_to_status(h->flag);
+  res->iters = h->k;
+  res->restarts = h->restarts;
+  res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  return true_residual(run, A, w, b, x, h, bb, res);
+}
+
+// --------------------------------------------------------------- Jacobi
+
+its_status check_diag(Run &run, its_matrix *A, const WS &w);
+
+its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const double *b, double *x,
+                        const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  double *X[2] = {x, w.v64(0)};
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, nullptr, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  LAUNCH(run, 7, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
+  // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
+  s = with_op64(A, [&](auto op) -> its_status {
+    return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
+      const int a = int(j & 1);
+      LAUNCH(run, 0, k_jacobi<decltype(op)>, G, op, b, (const double *)X[a], X[a ^ 1], w.st, w.partials, thr2, o->max_iter);
+      return ITS_OK;
+    });
+  });
+  if (s != ITS_OK) return s;
+  if (h->k & 1) HIP_TRY(hipMemcpyAsync(x, X[1], size_t(n) * 8, hipMemcpyDeviceToDevice, run.s));
+  HIP_TRY(hipStreamSynchronize(run.s));
+  res->status = flag_to_status(h->flag);
+  res->iters = h->k;
+  res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  res->true_rel_res = res->rel_res;
+  return ITS_OK;
+}
+
+// ----------------------------------------------------- symmetric Gauss-Seidel
+
+its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double *b, double *x,
+                     const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  const int nc = A->kind == kCsr ? A->ncolors : (A->kind == kSten7 ? 2 : 8);
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, nullptr, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  int32_t flag = kRunning;
+  if (rr <= thr2) flag = kConverged;
+  else if (!std::isfinite(rr)) flag = kBreakdown;
+  else if (o->max_iter <= 0) flag = kMaxIter;
+  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  // Colour order of iteration j: forward 0..nc-1 then backward nc-1..0.  The
+  // backward sweep's first colour repeats the forward sweep's last one on
+  // unchanged inputs, and the next forward sweep's colour 0 repeats this
+  // backward sweep's last one; both repeats reproduce identical bits and
+  // are skipped.
+  auto sweep = [&](int c) -> its_status {
+    if (A->kind == kCsr) {
+      const int32_t beg = A->color_off[c], cnt = A->color_off[c + 1] - beg;
+      if (cnt == 0) return ITS_OK;
+      LAUNCH(run, 0, k_gs_rows_csr, grid_for(cnt), CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, (const State *)w.st);
+    } else if (A->kind == kSten7) {
+      StencilOp<7, double> op{A->nx, A->ny, A->nz, n, {}};
+      for (int q = 0; q < 7; ++q) op.c[q] = A->coef[q];
+      LAUNCH(run, 0, k_gs_stencil<7>, G, op, (int32_t)c, b, x, (const State *)w.st);
+    } else {
+      StencilOp<27, double> op{A->nx, A->ny, A->nz, n, {}};
+      for (int q = 0; q < 27; ++q) op.c[q] = A->coef[q];
+      LAUNCH(run, 0, k_gs_stencil<27>, G, op, (int32_t)c, b, x, (const State *)w.st);
+    }
+    return ITS_OK;
+  };
+  if (flag == kRunning) {
+    s = with_op64(A, [&](auto op) -> its_status {
+      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
+        for (int c = (j == 0 ? 0 : 1); c < nc; ++c) {
+          its_status e = sweep(c);
+          if (e != ITS_OK) return e;
+        }
+        for (int c = nc - 2; c >= 0; --c) {
+          its_status e = sweep(c);
+          if (e != ITS_OK) return e;
+        }
+        LAUNCH(run, 1, k_gs_check<decltype(op)>, G, op, b, (const double *)x, w.st, w.partials, thr2, o->max_iter);
+        return ITS_OK;
+      });
+    });
+    if (s != ITS_OK) return s;
+  } else {
+    s = poll(run, w.st, h);
+    if (s != ITS_OK) return s;
+  }
+  res->status = flag_to_status(h->flag);
+  res->iters = h->k;
+  res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  res->true_rel_res = res->rel_res;
+  return ITS_OK;
+}
+
+its_status check_diag(Run &run, its_matrix *A, const WS &w) {
+  if (A->kind != kCsr) {
+    A->diag_state = A->coef[A->kind == kSten7 ? 3 : 13] != 0.0 ? 1 : -1;
+    return ITS_OK;
+  }
+  if (A->diag_state != 0) return ITS_OK;
+  uint32_t *bad = &w.st2->counter[7];
+  LAUNCH(run, 7, k_reset_state, 1, w.st2, 1);
+  LAUNCH(run, 7, k_csr_check, grid_for(A->n), int32_t(A->n), int32_t(A->nnz), A->rp, A->col, A->val, (int32_t)1, bad);
+  its_status s = poll(run, w.st2, A->host_state);
+  if (s != ITS_OK) return s;
+  A->diag_state = A->host_state->counter[7] == 0 ? 1 : -1;
+  return ITS_OK;
+}
+
+bool options_ok(const its_options *o, std::string &why) {
+  if (o->method < ITS_JACOBI || o->method > ITS_BICGSTAB) { why = "unknown method"; return false; }
+  if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) { why = "rtol must be finite and >= 0"; return false; }
+  if (o->max_iter < 0) { why = "max_iter must be >= 0"; return false; }
+  if (!(o->restart_tol >= 0.0) || !std::isfinite(o->restart_tol)) { why = "restart_tol must be finite and >= 0"; return false; }
+  if (o->restart_mode != ITS_RESTART_COSINE && o->restart_mode != ITS_RESTART_PAPER) { why = "unknown restart_mode"; return false; }
+  if (o->check_every < 0) { why = "check_every must be >= 0"; return false; }
+  if (o->inner_dtype < ITS_F64 || o->inner_dtype > ITS_F16) { why = "unknown inner_dtype"; return false; }
+  if (o->inner_dtype != ITS_F64 && o->method != ITS_CG) { why = "mixed precision is for CG only"; return false; }
+  if (!(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol)) { why = "inner_rtol must be finite and >= 0"; return false; }
+  if (o->max_outer < 0) { why = "max_outer must be >= 0"; return false; }
+  return true;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+void its_default_options(its_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->method = ITS_CG;
+  o->restart_mode = ITS_RESTART_COSINE;
+  o->rtol = 1e-8;
+  o->max_iter = 10000;
+  o->restart_tol = 1e-5;
+  o->check_every = 0;
+  o->inner_dtype = ITS_F64;
+  o->inner_rtol = 1e-4;
+  o->max_outer = 30;
+  o->profile = 0;
+}
+
+const char *its_status_string(int32_t st) {
+  switch (st) {
+    case ITS_OK: return "ITS_OK";
+    case ITS_NOT_CONVERGED: return "ITS_NOT_CONVERGED";
+    case ITS_BREAKDOWN: return "ITS_BREAKDOWN";
+    case ITS_E_INVALID: return "ITS_E_INVALID";
+    case ITS_E_HIP: return "ITS_E_HIP";
+    case ITS_E_WORKSPACE: return "ITS_E_WORKSPACE";
+    case ITS_E_UNSUPPORTED: return "ITS_E_UNSUPPORTED";
+    default: return "unknown status";
+  }
+}
+
+const char *its_last_error(void) { return g_err.c_str(); }
+
+static its_status new_matrix(its_matrix **out) {
+  its_matrix *A = new (std::nothrow) its_matrix();
+  if (!A) return fail(ITS_E_INVALID, "out of host memory");
+  void *p = nullptr;
+  if (hipHostMalloc(&p, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+    delete A;
+    return fail(ITS_E_HIP, "hipHostMalloc of the state snapshot failed");
+  }
+  A->host_state = static_cast<State *>(p);
+  std::memset(A->host_state, 0, sizeof(State));
+  *out = A;
+  return ITS_OK;
+}
+
+its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                          const double *val, its_matrix **out) {
+  if (!out) return fail(ITS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (n < 0 || nnz < 0) return fail(ITS_E_INVALID, "negative size");
+  if (n >= (int64_t(1) << 31) - 1 || nnz >= (int64_t(1) << 31))
+    return fail(ITS_E_UNSUPPORTED, "n and nnz must be below 2^31");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(ITS_E_INVALID, "null CSR array");
+  its_matrix *A;
+  its_status s = new_matrix(&A);
+  if (s != ITS_OK) return s;
+  A->kind = kCsr;
+  A->n = n;
+  A->nnz = nnz;
+  A->rp = row_ptr;
+  A->col = col;
+  A->val = val;
+  *out = A;
+  return ITS_OK;
+}
+
+its_status its_stencil_create(int32_t nx, int32_t ny, int32_t nz, int32_t npts, const double *coef,
+                              its_matrix **out) {
+  if (!out) return fail(ITS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (nx < 0 || ny < 0 || nz < 0) return fail(ITS_E_INVALID, "negative grid size");
+  if (npts != 7 && npts != 27) return fail(ITS_E_INVALID, "npts must be 7 or 27");
+  if (!coef) return fail(ITS_E_INVALID, "coef is null");
+  const int64_t n = int64_t(nx) * ny * nz;
+  if (n >= (int64_t(1) << 31) - 1) return fail(ITS_E_UNSUPPORTED, "grid must have < 2^31 nodes");
+  for (int o = 0; o < npts; ++o)
+    if (!std::isfinite(coef[o])) return fail(ITS_E_INVALID, "non-finite coefficient");
+  its_matrix *A;
+  its_status s = new_matrix(&A);
+  if (s != ITS_OK) return s;
+  A->kind = npts == 7 ? kSten7 : kSten27;
+  A->n = n;
+  A->nx = nx;
+  A->ny = ny;
+  A->nz = nz;
+  for (int o = 0; o < npts; ++o) A->coef[o] = coef[o];
+  *out = A;
+  return ITS_OK;
+}
+
+its_status its_matrix_destroy(its_matrix *A) {
+  if (!A) return ITS_OK;
+  if (A->color_rows) (void)hipFree(A->color_rows);
+  if (A->host_state) (void)hipHostFree(A->host_state);
+  delete A;
+  return ITS_OK;
+}
+
+int64_t its_matrix_rows(const its_matrix *A) { return A ? A->n : -1; }
+
+its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (A->n == 0) return ITS_OK;
+  uint32_t *bad = nullptr;
+  HIP_TRY(hipMalloc(&bad, sizeof(uint32_t)));
+  hipStream_t s = S(stream);
+  its_status rs = ITS_OK;
+  uint32_t hbad = 0;
+  do {
+    if (hipMemsetAsync(bad, 0, sizeof(uint32_t), s) != hipSuccess) { rs = fail(ITS_E_HIP, "memset"); break; }
+    hipLaunchKernelGGL(k_csr_check, dim3(grid_for(A->n)), dim3(kBlock), 0, s, int32_t(A->n),
+                       int32_t(A->nnz), A->rp, A->col, A->val, need_diag, bad);
+    if (hipGetLastError() != hipSuccess) { rs = fail(ITS_E_HIP, "launch k_csr_check"); break; }
+    if (hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { rs = fail(ITS_E_HIP, "readback"); break; }
+  } while (0);
+  (void)hipFree(bad);
+  if (rs != ITS_OK) return rs;
+  if (need_diag) A->diag_state = hbad == 0 ? 1 : -1;
+  if (hbad) return fail(ITS_E_INVALID, std::to_string(hbad) + " invalid CSR rows");
+  return ITS_OK;
+}
+
+its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (!val_lo && A->nnz > 0) return fail(ITS_E_INVALID, "null values");
+  if (dtype == ITS_F32) A->val32 = static_cast<const float *>(val_lo);
+  else if (dtype == ITS_F16) A->val16 = static_cast<const __half *>(val_lo);
+  else return fail(ITS_E_INVALID, "dtype must be ITS_F32 or ITS_F16");
+  return ITS_OK;
+}
+
+its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolors, void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (ncolors < 1 || ncolors > 255) return fail(ITS_E_INVALID, "ncolors must be in 1..255");
+  if (!color && A->n > 0) return fail(ITS_E_INVALID, "color is null");
+  hipStream_t s = S(stream);
+  const int64_t n = A->n;
+  std::vector<uint8_t> hc(static_cast<size_t>(n));
+  if (n > 0) {
+    uint32_t *bad = nullptr;
+    HIP_TRY(hipMalloc(&bad, sizeof(uint32_t)));
+    uint32_t hbad = 0;
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(uint32_t), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_color_check, dim3(grid_for(n)), dim3(kBlock), 0, s, int32_t(n), A->rp,
+                         A->col, color, ncolors, bad);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), color, size_t(n), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(ITS_E_HIP, std::string("colour check: ") + hipGetErrorString(e));
+    if (hbad) return fail(ITS_E_INVALID, std::to_string(hbad) + " rows violate the colouring");
+  }
+  // group rows by colour (counting sort, ascending rows within a colour)
+  std::vector<int32_t> off(static_cast<size_t>(ncolors) + 1, 0);
+  std::vector<int32_t> rows(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) off[hc[size_t(i)] + 1]++;
+  for (int c = 0; c < ncolors; ++c) off[c + 1] += off[c];
+  std::vector<int32_t> pos(off.begin(), off.end() - 1);
+  for (int64_t i = 0; i < n; ++i) rows[size_t(pos[hc[size_t(i)]]++)] = int32_t(i);
+  int32_t *d = nullptr;
+  if (n > 0) {
+    HIP_TRY(hipMalloc(&d, size_t(n) * sizeof(int32_t)));
+    if (hipMemcpy(d, rows.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return fail(ITS_E_HIP, "upload of colour rows failed");
+    }
+  }
+  if (A->color_rows) (void)hipFree(A->color_rows);
+  A->color_rows = d;
+  A->color_off = off;
+  A->ncolors = ncolors;
+  return ITS_OK;
+}
+
+its_status its_spmv(const its_matrix *A, const double *x, double *y, void *stream) {
+  if (!A) return fail(ITS_E_INVALID, "A is null");
+  if (A->n == 0) return ITS_OK;
+  if (!x || !y) return fail(ITS_E_INVALID, "null vector");
+  if (x == y) return fail(ITS_E_INVALID, "x and y alias");
+  const int64_t tiles = (A->n + kBlock - 1) / kBlock;
+  const int grid = int(std::min<int64_t>(tiles, int64_t(1) << 30));
+  hipStream_t s = S(stream);
+  its_status st = with_op64(A, [&](auto op) -> its_status {
+    hipLaunchKernelGGL(k_spmv<decltype(op)>, dim3(grid), dim3(kBlock), 0, s, op, x, y);
+    return ITS_OK;
+  });
+  if (st != ITS_OK) return st;
+  HIP_TRY(hipGetLastError());
+  return ITS_OK;
+}
+
+size_t its_dot_workspace_size(int64_t) {
+  return up(sizeof(State)) + up(sizeof(DD) * kMaxDots * kMaxGrid);
+}
+
+its_status its_dot(int64_t n, const double *x, const double *y, double *result, void *workspace,
+                   size_t ws_bytes, void *stream) {
+  if (!result) return fail(ITS_E_INVALID, "result is null");
+  if (n < 0) return fail(ITS_E_INVALID, "negative n");
+  if (n >= (int64_t(1) << 31) - 1) return fail(ITS_E_UNSUPPORTED, "n must be below 2^31");
+  if (n > 0 && (!x || !y)) return fail(ITS_E_INVALID, "null vector");
+  if (!workspace || ws_bytes < its_dot_workspace_size(n))
+    return fail(ITS_E_WORKSPACE, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ITS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  State *st = static_cast<State *>(workspace);
+  DD *partials = reinterpret_cast<DD *>(static_cast<char *>(workspace) + up(sizeof(State)));
+  hipStream_t s = S(stream);
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(kBlock), 0, s, st, 1);
+  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, int32_t(n), x, y, st, partials, 0, 0);
+  HIP_TRY(hipGetLastError());
+  double v = 0.0;
+  HIP_TRY(hipMemcpyAsync(&v, &st->dot[0], sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *result = v;
+  return ITS_OK;
+}
+
+its_status its_workspace_size(const its_matrix *A, const its_options *o, size_t *bytes) {
+  if (!A || !o || !bytes) return fail(ITS_E_INVALID, "null argument");
+  std::string why;
+  if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
+  *bytes = layout_for(A->n, o->method, o->inner_dtype).total;
+  return ITS_OK;
+}
+
+its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b, double *x,
+                     void *workspace, size_t ws_bytes, void *stream, its_result *res) {
+  its_matrix *A = const_cast<its_matrix *>(Ac);  // only cached validation state changes
+  if (!A || !o || !res) return fail(ITS_E_INVALID, "null argument");
+  std::string why;
+  if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
+  if (A->n > 0 && (!b || !x)) return fail(ITS_E_INVALID, "null vector");
+  if (A->n > 0 && b == x) return fail(ITS_E_INVALID, "b and x alias");
+  const Layout L = layout_for(A->n, o->method, o->inner_dtype);
+  if (!workspace || ws_bytes < L.total) return fail(ITS_E_WORKSPACE, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ITS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if ((o->method == ITS_SGS) && A->kind == kCsr && A->ncolors == 0)
+    return fail(ITS_E_INVALID, "Gauss-Seidel on CSR needs its_csr_set_colors");
+  std::memset(res, 0, sizeof(*res));
+  if (A->n == 0) {
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  Run run;
+  run.s = S(stream);
+  run.prof.on = o->profile != 0;
+  run.prof.res = res;
+  const WS w = carve(workspace, L, A->n);
+  if (o->method == ITS_JACOBI || o->method == ITS_SGS) {
+    its_status s = check_diag(run, A, w);
+    if (s != ITS_OK) return s;
+    if (A->diag_state < 0) return fail(ITS_E_INVALID, "a row lacks a nonzero diagonal entry");
+  }
+  its_status s;
+  switch (o->method) {
+    case ITS_CG:
+      s = o->inner_dtype == ITS_F64 ? solve_cg(run, A, o, b, x, w, res) : solve_ir(run, A, o, b, x, w, res);
+      break;
+    case ITS_BICGSTAB: s = solve_bicgstab(run, A, o, b, x, w, res); break;
+    case ITS_JACOBI: s = solve_jacobi(run, A, o, b, x, w, res); break;
+    default: s = solve_sgs(run, A, o, b, x, w, res); break;
+  }
+  if (s != ITS_OK) return s;
+  return static_cast<its_status>(res->status);
+}
+
+its_status its_cast_values(const double *src, void *dst, int32_t dtype, int64_t count, void *stream) {
+  if (count < 0) return fail(ITS_E_INVALID, "negative count");
+  if (count == 0) return ITS_OK;
+  if (!src || !dst) return fail(ITS_E_INVALID, "null pointer");
+  const int grid = int(std::min<int64_t>((count + kBlock - 1) / kBlock, 65536));
+  hipStream_t s = S(stream);
+  if (dtype == ITS_F32)
+    hipLaunchKernelGGL(k_cast_f32, dim3(grid), dim3(kBlock), 0, s, count, src, static_cast<float *>(dst));
+  else if (dtype == ITS_F16)
+    hipLaunchKernelGGL(k_cast_f16, dim3(grid), dim3(kBlock), 0, s, count, src, static_cast<_Float16 *>(dst));
+  else
+    return fail(ITS_E_INVALID, "dtype must be ITS_F32 or ITS_F16");
+  HIP_TRY(hipGetLastError());
+  return ITS_OK;
+}
+
+its_status its_stream_copy(const double *src, double *dst, int64_t n, void *stream) {
+  if (n < 0) return fail(ITS_E_INVALID, "negative n");
+  if (n == 0) return ITS_OK;
+  if (!src || !dst) return fail(ITS_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+    return fail(ITS_E_INVALID, "copy buffers must be 16-byte aligned");
+  const int grid = int(std::min<int64_t>((n / 2 + kBlock - 1) / kBlock + 1, 8192));
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, S(stream), n, src, dst);
+  HIP_TRY(hipGetLastError());
+  return ITS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,405 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs.
+
+Bars: SpMV, Jacobi and Gauss-Seidel iterates bit-exact (identical fma chains
+and IEEE division); dot products equal to the correctly rounded value
+(double-double accumulation); CG and BiCGStab iterates within 1e-10
+relative of the oracle with iteration counts within +-1 (the scalars come
+from the same correctly rounded dots, so the iterates are expected to match
+bit for bit, and the tests report the largest difference in ulps).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_05988_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def its():
+    import paper_2305_05988_amd as m
+    return m
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def ulps(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    ia = a.view(np.int64)
+    ib = b.view(np.int64)
+    ia = np.where(ia < 0, np.int64(-2 ** 63) - ia, ia)
+    ib = np.where(ib < 0, np.int64(-2 ** 63) - ib, ib)
+    return int(np.max(np.abs(ia - ib))) if a.size else 0
+
+
+def rel(a, b):
+    d = np.max(np.abs(np.asarray(a) - np.asarray(b)))
+    s = np.max(np.abs(b))
+    return d / s if s > 0 else d
+
+
+GRIDS7 = [(1, 1, 1), (5, 3, 2), (17, 9, 5), (32, 32, 32), (33, 20, 7)]
+
+
+# ------------------------------------------------------------------ kernels
+
+@pytest.mark.parametrize("n", [1, 63, 256, 257, 4099, 65536 * 3 + 17, 1 << 21])
+def test_dot_is_correctly_rounded(n):
+    x = inputs.uniform_vector(n, 10)
+    y = inputs.uniform_vector(n, 11) * 1e3
+    got = its().dot(dev(x), dev(y))
+    assert got == oracle.dot(x, y)
+
+
+def test_dot_under_cancellation():
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(100000) * 2.0 ** rng.integers(-40, 40, 100000)
+    y = rng.standard_normal(100000)
+    x2 = np.concatenate([x, -x, [1e-20]])
+    y2 = np.concatenate([y, y, [1.0]])
+    # a condition number ~1e31 is beyond double-double: the documented bound
+    # n 2^-104 sum|x_i y_i| + half an ulp of the exact value applies
+    got, exact = its().dot(dev(x2), dev(y2)), oracle.dot(x2, y2)
+    bound = x2.size * 2.0 ** -104 * np.sum(np.abs(x2 * y2)) + 2.0 ** -53 * abs(exact)
+    assert abs(got - exact) <= bound
+
+
+@pytest.mark.parametrize("g", GRIDS7)
+@pytest.mark.parametrize("kind", ["poisson7", "convdiff7", "stencil27"])
+def test_spmv_bit_exact_csr_and_stencil(g, kind):
+    gen = {"poisson7": inputs.poisson7_csr, "convdiff7": inputs.convdiff7_csr,
+           "stencil27": inputs.stencil27_csr}[kind]
+    coef = {"poisson7": inputs.POISSON7, "convdiff7": inputs.convdiff7(),
+            "stencil27": inputs.STENCIL27}[kind]
+    Acsr = gen(*g)
+    n = Acsr[0].size - 1
+    x = inputs.uniform_vector(n, 3)
+    ref = oracle.spmv(Acsr, x)
+    A = its().CSRMatrix.from_numpy(*Acsr)
+    assert np.array_equal(host(its().spmv(A, dev(x))), ref)
+    S = its().StencilMatrix(*g, coef)
+    assert np.array_equal(host(its().spmv(S, dev(x))), ref)
+
+
+def test_spmv_empty_and_ragged_rows():
+    # rows 1 and 3 empty, ragged lengths
+    rp = np.array([0, 3, 3, 4, 4, 7], np.int64)
+    col = np.array([0, 2, 4, 1, 0, 3, 4], np.int32)
+    val = np.array([1.5, -2.0, 0.25, 3.0, -1.0, 2.0, 0.5])
+    x = inputs.uniform_vector(5, 4)
+    A = its().CSRMatrix.from_numpy(rp, col, val)
+    assert np.array_equal(host(its().spmv(A, dev(x))), oracle.spmv((rp, col, val), x))
+
+
+def test_cast_values_round_to_nearest():
+    v = np.concatenate([inputs.uniform_vector(10000, 5) * 100, [26.0, -1.0, 1 + 2 ** -11 + 2 ** -30]])
+    t = dev(v)
+    assert np.array_equal(host(its().cast_values(t, "f32")), v.astype(np.float32))
+    assert np.array_equal(host(its().cast_values(t, "f16")), v.astype(np.float16))
+
+
+def test_stream_copy():
+    v = inputs.uniform_vector(1000001, 6)
+    src = dev(v)
+    dst = torch.empty_like(src)
+    its().stream_copy(src, dst)
+    assert np.array_equal(host(dst), v)
+
+
+# ---------------------------------------------------------------------- CG
+
+def _system(Acsr, seed=1):
+    n = Acsr[0].size - 1
+    xs = inputs.uniform_vector(n, seed)
+    return xs, oracle.spmv(Acsr, xs)
+
+
+def _matrix(kind, g):
+    if kind == "csr7":
+        Acsr = inputs.poisson7_csr(*g)
+        return Acsr, its().CSRMatrix.from_numpy(*Acsr, lowp=("f32", "f16"))
+    if kind == "sten7":
+        return inputs.poisson7_csr(*g), its().StencilMatrix(*g, inputs.POISSON7)
+    if kind == "csr27":
+        Acsr = inputs.stencil27_csr(*g)
+        return Acsr, its().CSRMatrix.from_numpy(*Acsr, lowp=("f32", "f16"))
+    if kind == "sten27":
+        return inputs.stencil27_csr(*g), its().StencilMatrix(*g, inputs.STENCIL27)
+    if kind == "csrcd":
+        Acsr = inputs.convdiff7_csr(*g)
+        return Acsr, its().CSRMatrix.from_numpy(*Acsr)
+    if kind == "stencd":
+        return inputs.convdiff7_csr(*g), its().StencilMatrix(*g, inputs.convdiff7())
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27"])
+@pytest.mark.parametrize("k", [1, 2, 7, 40])
+def test_cg_fixed_k_iterates(kind, k):
+    Acsr, A = _matrix(kind, (19, 13, 11))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.cg(Acsr, b, rtol=0.0, max_iter=k)
+    x, info = its().solve(A, dev(b), method="cg", rtol=0.0, max_iter=k)
+    xg = host(x)
+    assert info.status == "not_converged" and info.iters == k == rr.iters
+    assert rel(xg, ref) <= 1e-10, f"max ulps {ulps(xg, ref)}"
+    assert ulps(xg, ref) == 0
+
+
+@pytest.mark.parametrize("kind", ["csr7", "sten7"])
+def test_cg_converged_32cube(kind):
+    Acsr, A = _matrix(kind, (32, 32, 32))
+    xs, b = _system(Acsr, seed=1)
+    ref, rr = oracle.cg(Acsr, b, rtol=1e-8, max_iter=5000)
+    x, info = its().solve(A, dev(b), method="cg", rtol=1e-8, max_iter=5000)
+    xg = host(x)
+    assert rr.status == oracle.OK and info.status == "ok"
+    assert abs(info.iters - rr.iters) <= 1
+    assert rel(xg, ref) <= 1e-10
+    assert info.true_rel_res <= 1.01e-8
+    print(f"CG 32^3 {kind}: iters {info.iters} (oracle {rr.iters}), max ulps {ulps(xg, ref)}")
+
+
+@pytest.mark.parametrize("check_every", [1, 3, 64])
+def test_cg_polling_interval_does_not_change_result(check_every):
+    Acsr, A = _matrix("csr7", (16, 16, 16))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.cg(Acsr, b, rtol=1e-9, max_iter=1000)
+    x, info = its().solve(A, dev(b), method="cg", rtol=1e-9, max_iter=1000, check_every=check_every)
+    assert info.iters == rr.iters and ulps(host(x), ref) == 0
+
+
+def test_cg_nonzero_initial_guess():
+    Acsr, A = _matrix("csr7", (12, 12, 12))
+    xs, b = _system(Acsr)
+    x0 = inputs.uniform_vector(xs.size, 77)
+    ref, rr = oracle.cg(Acsr, b, x0=x0, rtol=1e-9, max_iter=1000)
+    x, info = its().solve(A, dev(b), x0=dev(x0), method="cg", rtol=1e-9, max_iter=1000)
+    assert info.iters == rr.iters and rel(host(x), ref) <= 1e-10
+
+
+# ------------------------------------------------------------------ Jacobi
+
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csrcd", "sten27"])
+@pytest.mark.parametrize("k", [0, 1, 2, 25])
+def test_jacobi_fixed_k_bit_exact(kind, k):
+    Acsr, A = _matrix(kind, (17, 9, 6))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.jacobi(Acsr, b, rtol=0.0, max_iter=k)
+    x, info = its().solve(A, dev(b), method="jacobi", rtol=0.0, max_iter=k)
+    assert info.iters == rr.iters == k
+    assert np.array_equal(host(x), ref)
+
+
+def test_jacobi_32cube_cap_binds():
+    # rho_J = cos(pi/33) = 0.99547: 1e-8 needs ~4000 sweeps, so the cap of
+    # 2000 binds and parity is at exactly 2000 sweeps
+    Acsr, A = _matrix("csr7", (32, 32, 32))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.jacobi(Acsr, b, rtol=1e-8, max_iter=2000)
+    x, info = its().solve(A, dev(b), method="jacobi", rtol=1e-8, max_iter=2000)
+    assert rr.status == oracle.NOT_CONVERGED and info.status == "not_converged"
+    assert info.iters == rr.iters == 2000
+    assert np.array_equal(host(x), ref)
+
+
+def test_jacobi_converges_upwind():
+    Acsr, A = _matrix("stencd", (20, 20, 20))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.jacobi(Acsr, b, rtol=1e-8, max_iter=500)
+    x, info = its().solve(A, dev(b), method="jacobi", rtol=1e-8, max_iter=500)
+    assert rr.status == oracle.OK and info.status == "ok" and info.iters == rr.iters
+    assert np.array_equal(host(x), ref)
+
+
+# ------------------------------------------------------------ Gauss-Seidel
+
+@pytest.mark.parametrize("k", [1, 2, 9])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "sten27"])
+def test_sgs_fixed_k_bit_exact(kind, k):
+    g = (11, 7, 6)
+    Acsr, A = _matrix(kind, g)
+    xs, b = _system(Acsr)
+    nc = 8 if "27" in kind else 2
+    col = inputs.redblack_colors(*g) if nc == 2 else inputs.octant_colors(*g)
+    if kind.startswith("csr"):
+        A.set_colors(col, nc)
+    ref, rr = oracle.sgs(Acsr, col, nc, b, rtol=0.0, max_iter=k)
+    x, info = its().solve(A, dev(b), method="sgs", rtol=0.0, max_iter=k)
+    assert info.iters == rr.iters == k
+    assert np.array_equal(host(x), ref)
+
+
+def test_sgs_converged_32cube_redblack():
+    g = (32, 32, 32)
+    Acsr, A = _matrix("csr7", g)
+    xs, b = _system(Acsr)
+    col = inputs.redblack_colors(*g)
+    A.set_colors(col, 2)
+    ref, rr = oracle.sgs(Acsr, col, 2, b, rtol=1e-8, max_iter=5000)
+    x, info = its().solve(A, dev(b), method="sgs", rtol=1e-8, max_iter=5000)
+    assert rr.status == oracle.OK and info.status == "ok" and info.iters == rr.iters
+    assert np.array_equal(host(x), ref)
+    S = its().StencilMatrix(*g, inputs.POISSON7)
+    x2, info2 = its().solve(S, dev(b), method="sgs", rtol=1e-8, max_iter=5000)
+    assert info2.iters == rr.iters and np.array_equal(host(x2), ref)
+
+
+def test_sgs_rejects_bad_colouring():
+    g = (6, 6, 6)
+    Acsr, A = _matrix("csr27", g)
+    with pytest.raises(its().ItsError):
+        A.set_colors(inputs.redblack_colors(*g), 2)
+
+
+# --------------------------------------------------------------- BiCGStab
+
+@pytest.mark.parametrize("kind", ["csrcd", "stencd", "csr7"])
+@pytest.mark.parametrize("k", [1, 3, 12])
+def test_bicgstab_fixed_k(kind, k):
+    Acsr, A = _matrix(kind, (18, 11, 9))
+    xs, b = _system(Acsr, seed=2)
+    ref, rr = oracle.bicgstab(Acsr, b, rtol=0.0, max_iter=k)
+    x, info = its().solve(A, dev(b), method="bicgstab", rtol=0.0, max_iter=k)
+    xg = host(x)
+    assert info.iters == rr.iters == k
+    assert rel(xg, ref) <= 1e-10, f"max ulps {ulps(xg, ref)}"
+    assert ulps(xg, ref) == 0
+
+
+@pytest.mark.parametrize("kind", ["csrcd", "stencd"])
+def test_bicgstab_converged(kind):
+    Acsr, A = _matrix(kind, (40, 36, 30))
+    xs, b = _system(Acsr, seed=1)
+    ref, rr = oracle.bicgstab(Acsr, b, rtol=1e-8, max_iter=1000)
+    x, info = its().solve(A, dev(b), method="bicgstab", rtol=1e-8, max_iter=1000)
+    assert rr.status == oracle.OK and info.status == "ok"
+    assert abs(info.iters - rr.iters) <= 1 and rel(host(x), ref) <= 1e-10
+    assert info.true_rel_res <= 1.01e-8
+
+
+@pytest.mark.parametrize("mode,tol", [("cosine", 0.9), ("paper", 30.0)])
+def test_bicgstab_restart_paths(mode, tol):
+    Acsr, A = _matrix("csrcd", (14, 12, 10))
+    xs, b = _system(Acsr, seed=8)
+    rm = oracle.RESTART_COSINE if mode == "cosine" else oracle.RESTART_PAPER
+    ref, rr = oracle.bicgstab(Acsr, b, rtol=1e-10, max_iter=2000, restart_tol=tol, restart_mode=rm)
+    x, info = its().solve(A, dev(b), method="bicgstab", rtol=1e-10, max_iter=2000,
+                          restart_tol=tol, restart_mode=mode)
+    assert rr.restarts > 0 and info.restarts == rr.restarts
+    assert info.iters == rr.iters and rel(host(x), ref) <= 1e-10
+
+
+# ---------------------------------------------------- mixed precision (IR)
+
+@pytest.mark.parametrize("kind", ["csr27", "sten27", "csr7"])
+@pytest.mark.parametrize("lowp", ["f32", "f16"])
+def test_ir_cg_matches_oracle(kind, lowp):
+    g = (24, 20, 18)
+    Acsr, A = _matrix(kind, g)
+    xs, b = _system(Acsr, seed=1)
+    lo = Acsr[2].astype(np.float32 if lowp == "f32" else np.float16)
+    ref, rr = oracle.ir_cg(Acsr, lo, b, rtol=1e-10, max_iter=5000, inner_rtol=1e-4)
+    x, info = its().solve(A, dev(b), method="cg", rtol=1e-10, max_iter=5000,
+                          inner_dtype=lowp, inner_rtol=1e-4)
+    xg = host(x)
+    assert rr.status == oracle.OK and info.status == "ok"
+    assert info.iters == rr.iters and info.inner_iters == rr.inner_iters
+    assert rel(xg, ref) <= 1e-10
+    x64, r64 = oracle.cg(Acsr, b, rtol=1e-12, max_iter=5000)
+    err = np.linalg.norm(xg - x64) / np.linalg.norm(x64)
+    print(f"IR {kind} {lowp}: outer {info.iters} inner {info.inner_iters}, "
+          f"error vs FP64 oracle {err:.2e}, ulps vs IR oracle {ulps(xg, ref)}")
+    assert err <= 1e-8
+
+
+# ------------------------------------------------------- edge cases / status
+
+@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab"])
+def test_zero_rhs(method):
+    A = its().StencilMatrix(5, 4, 3, inputs.POISSON7)
+    x, info = its().solve(A, torch.zeros(60, dtype=torch.float64, device="cuda"),
+                          x0=torch.ones(60, dtype=torch.float64, device="cuda"), method=method)
+    assert info.status == "ok" and info.iters == 0 and not host(x).any()
+
+
+@pytest.mark.parametrize("method", ["jacobi", "cg", "bicgstab"])
+def test_nan_rhs_is_invalid(method):
+    A = its().StencilMatrix(5, 4, 3, inputs.POISSON7)
+    b = np.ones(60)
+    b[7] = np.nan
+    with pytest.raises(its().ItsError) as e:
+        its().solve(A, dev(b), method=method)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab"])
+def test_max_iter_zero(method):
+    Acsr, A = _matrix("sten7", (6, 5, 4))
+    xs, b = _system(Acsr)
+    x, info = its().solve(A, dev(b), method=method, rtol=1e-8, max_iter=0)
+    assert info.status == "not_converged" and info.iters == 0 and not host(x).any()
+
+
+def test_single_unknown():
+    A = its().CSRMatrix.from_numpy(np.array([0, 1]), np.array([0]), np.array([4.0]))
+    for method in ("jacobi", "cg", "bicgstab"):
+        x, info = its().solve(A, dev(np.array([3.0])), method=method, rtol=1e-14, max_iter=10)
+        assert info.status == "ok" and host(x)[0] == 0.75
+
+
+def test_cg_breakdown_on_indefinite():
+    A = its().CSRMatrix.from_numpy(np.array([0, 1, 2]), np.array([0, 1]), np.array([1.0, -1.0]))
+    x, info = its().solve(A, dev(np.array([1.0, 1.0])), method="cg")
+    assert info.status == "breakdown" and info.iters == 0
+
+
+def test_bicgstab_breakdown_alpha_d_zero():
+    A = its().CSRMatrix.from_numpy(np.array([0, 1, 2]), np.array([1, 0]), np.array([1.0, 1.0]))
+    x, info = its().solve(A, dev(np.array([1.0, 0.0])), method="bicgstab")
+    assert info.status == "breakdown" and info.iters == 0
+
+
+def test_jacobi_rejects_missing_diagonal():
+    A = its().CSRMatrix.from_numpy(np.array([0, 1, 2]), np.array([1, 0]), np.array([1.0, 1.0]))
+    with pytest.raises(its().ItsError):
+        its().solve(A, dev(np.array([1.0, 0.0])), method="jacobi")
+
+
+def test_invalid_csr_rejected():
+    with pytest.raises(its().ItsError):
+        its().CSRMatrix.from_numpy(np.array([0, 2, 3]), np.array([1, 0, 5]), np.ones(3))
+
+
+def test_empty_system():
+    A = its().StencilMatrix(0, 4, 4, inputs.POISSON7)
+    x, info = its().solve(A, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert info.status == "ok" and x.numel() == 0
+
+
+def test_workspace_too_small():
+    A = its().StencilMatrix(8, 8, 8, inputs.POISSON7)
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    from paper_2305_05988_amd import api
+    with pytest.raises(its().ItsError) as e:
+        import ctypes as C
+        r = api.L.Result()
+        o = api.options()
+        b = torch.ones(512, dtype=torch.float64, device="cuda")
+        x = torch.zeros_like(b)
+        api.L.check(api.L.lib().its_solve(A.handle, C.byref(o), api._ptr(b), api._ptr(x),
+                                          api._ptr(ws), 1024, api._stream(), C.byref(r)), "solve")
+    assert e.value.status == -3
