@@ -1,0 +1,266 @@
+"""Benchmark: FP64 CG on the 256^3 Poisson 7-point CSR system to relative
+residual 1e-8 (x* ~ U[-1,1) seed 1, b = A x*, x0 = 0), one MI355X.
+
+A step is one complete solve.  The JSON line reports CG iterations per
+second over the timed steps, the roofline of the dominant kernel (the fused
+SpMV + dot pass) from HIP events recorded around every launch inside the
+timed region, the oracle timed on the host, and -- beside the metric -- the
+mixed-precision refinement against FP64 CG at 1e-8 plus the other methods of
+the library on their workloads.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "CG iters/s + achieved HBM GB/s, 256^3 Poisson; mixed-prec vs FP64 at 1e-8"
+KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/kernels.hpp", "paper_2305_05988_amd/csrc/common.hpp",
+                  "paper_2305_05988_amd/csrc/ops.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_pass1_poisson256_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def csr_bytes(n, nnz, val_bytes=8):
+    """Matrix bytes read per application: values, int32 columns, int32 row_ptr."""
+    return val_bytes * nnz + 4 * nnz + 4 * (n + 1)
+
+
+def measured_traffic(sha):
+    """HBM bytes per launch of the SpMV pass from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        m = re.match(r"TRAFFIC\s+(.*)", line.strip())
+        if m:
+            kv = dict(t.split("=", 1) for t in m.group(1).split())
+            if kv.get("src_sha") == sha:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
+def cpu_baseline(steps_small=3, steps_large=13):
+    """The oracle's CG on the same 256^3 system, single-threaded, timed as the
+    difference of two runs so the per-iteration rate excludes setup."""
+    import oracle
+    from paper_2305_05988_amd import inputs
+    A = inputs.poisson7_csr(256)
+    xs = inputs.uniform_vector(A[0].size - 1, 1)
+    b = oracle.spmv(A, xs)
+    times = {}
+    for k in (steps_small, steps_large):
+        t0 = time.perf_counter()
+        oracle.cg(A, b, rtol=0.0, max_iter=k)
+        times[k] = time.perf_counter() - t0
+    per_it = (times[steps_large] - times[steps_small]) / (steps_large - steps_small)
+    return {"value": 1.0 / per_it, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps_large - steps_small} FP64 CG iterations of the 256^3 Poisson CSR "
+                      f"system (difference of {steps_large}- and {steps_small}-iteration runs, "
+                      f"single thread)",
+            "seconds": times[steps_small] + times[steps_large]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--n", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
+              f"runs one GPU's whole subdomain; multi-GPU sharding is design-only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2305_05988_amd as its
+    from paper_2305_05988_amd import _lib, inputs
+
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    torch.cuda.set_device(0)
+    N = args.n
+    t0 = time.perf_counter()
+    rp, col, val = inputs.poisson7_csr(N)
+    n, nnz = rp.size - 1, col.size
+    A = its.CSRMatrix.from_numpy(rp, col, val)
+    del rp, col, val
+    xs = torch.from_numpy(inputs.uniform_vector(n, 1)).cuda()
+    b = its.spmv(A, xs)
+    torch.cuda.synchronize()
+    log(f"setup {N}^3 CSR n={n} nnz={nnz} in {time.perf_counter() - t0:.1f}s")
+
+    M = csr_bytes(n, nnz)
+    V = 8 * n
+    bytes_iter = M + 10 * V
+    bytes_pass1 = M + 3 * V  # read col, val, row_ptr, r and p (gathered); write q
+    bytes_pass2 = 7 * V      # read x, r, p, q; write x, r, p
+
+    opts = dict(method="cg", rtol=args.rtol, max_iter=20000)
+    ws = torch.empty(its.api.workspace_bytes(A, **opts), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        x, info = its.solve(A, b, workspace=ws, profile=True, **opts)
+    torch.cuda.synchronize()
+    iters = 0
+    ms1 = ms2 = 0.0
+    l1 = l2 = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, info = its.solve(A, b, workspace=ws, profile=True, **opts)
+        iters += info.iters
+        ms1 += info.kernel_ms[0]
+        ms2 += info.kernel_ms[1]
+        l1 += info.kernel_launches[0]
+        l2 += info.kernel_launches[1]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert info.status == "ok", info
+    its_per_s = iters / dt
+    avg1 = ms1 / max(l1, 1) * 1e-3
+    avg2 = ms2 / max(l2, 1) * 1e-3
+    sha = kernel_source_sha()
+    traffic = measured_traffic(sha)
+    roof = {"bound": "hbm", "kernel": "k_cg_pass1 (CSR SpMV + p.q)",
+            "achieved": bytes_pass1 / avg1 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": bytes_pass1 / avg1 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": bytes_pass1, "avg_launch_us": avg1 * 1e6,
+            "launches": l1, "kernel_src_sha": sha,
+            "update_pass": {"kernel": "k_cg_pass2", "avg_launch_us": avg2 * 1e6,
+                            "achieved": bytes_pass2 / avg2 / 1e9}}
+    xerr = (x - xs).norm().item() / xs.norm().item()
+    result = {
+        "metric": METRIC, "value": its_per_s, "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"poisson7_{N}^3_csr_fp64_cg_rtol{args.rtol:g}", "n": n,
+                   "nnz": nnz, "x_star": "U[-1,1) seed 1", "b": "A x*", "x0": 0,
+                   "iters_per_solve": info.iters},
+        "achieved_gbs": its_per_s * bytes_iter / 1e9,
+        "hbm_frac": its_per_s * bytes_iter / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_iter": bytes_iter,
+        "true_rel_res": info.true_rel_res, "rel_err_vs_xstar": xerr,
+        "roofline": roof,
+    }
+    log(f"CG {N}^3: {info.iters} it/solve, {its_per_s:.1f} it/s, "
+        f"{result['achieved_gbs']:.0f} GB/s ({result['hbm_frac']:.3f} of peak); pass1 "
+        f"{avg1 * 1e6:.1f} us ({roof['achieved']:.0f} GB/s), pass2 {avg2 * 1e6:.1f} us")
+
+    if not args.no_extras:
+        result["extras"] = extras(its, inputs, A, b, xs, n, nnz, N, args, ws, float(dt / iters))
+    del ws
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline()
+        log(f"cpu baseline {result['cpu_baseline']['value']:.3f} it/s")
+    print(json.dumps(result), flush=True)
+
+
+def timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
+    import torch
+    ex = {}
+    V = 8 * n
+    # mixed-precision refinement vs FP64 CG, same system, same tolerance
+    A.set_lowp(its.cast_values(A.val, "f32"))
+    A.set_lowp(its.cast_values(A.val, "f16"))
+    t64, (x64, i64) = timed(lambda: its.solve(A, b, method="cg", rtol=args.rtol, max_iter=20000))
+    mp = {"fp64_cg_s": t64, "fp64_iters": i64.iters}
+    for lowp in ("f32", "f16"):
+        its.solve(A, b, method="cg", rtol=args.rtol, max_iter=20000, inner_dtype=lowp,
+                  inner_rtol=1e-4)
+        t, (xl, il) = timed(lambda: its.solve(A, b, method="cg", rtol=args.rtol, max_iter=20000,
+                                              inner_dtype=lowp, inner_rtol=1e-4))
+        mp[f"ir_{lowp}_s"] = t
+        mp[f"ir_{lowp}_outer"] = il.iters
+        mp[f"ir_{lowp}_inner"] = il.inner_iters
+        mp[f"ir_{lowp}_true_rel_res"] = il.true_rel_res
+        mp[f"ir_{lowp}_speedup_vs_fp64"] = t64 / t
+        mp[f"ir_{lowp}_rel_diff_vs_fp64_cg"] = (xl - x64).norm().item() / x64.norm().item()
+    ex["mixed_precision_256"] = mp
+    log(f"mixed precision: {json.dumps(mp)}")
+    # matrix-free stencil CG on the same grid
+    S = its.StencilMatrix(N, N, N, inputs.POISSON7)
+    its.solve(S, b, method="cg", rtol=args.rtol, max_iter=20000)
+    t, (xs_, info) = timed(lambda: its.solve(S, b, method="cg", rtol=args.rtol, max_iter=20000))
+    ex["stencil_cg_256"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t,
+                            "achieved_gbs": info.iters / t * 10 * V / 1e9}
+    # Jacobi: 2000 capped sweeps on the CSR system
+    its.solve(A, b, method="jacobi", rtol=args.rtol, max_iter=50)
+    t, (xj, info) = timed(lambda: its.solve(A, b, method="jacobi", rtol=args.rtol, max_iter=500))
+    M = 12 * nnz + 4 * (n + 1)
+    ex["jacobi_256_csr"] = {"sweeps": info.iters, "s": t, "sweeps_per_s": info.iters / t,
+                            "achieved_gbs": info.iters / t * (M + 3 * V) / 1e9}
+    # red-black symmetric Gauss-Seidel, matrix-free
+    its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=5)
+    t, (xg, info) = timed(lambda: its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=200))
+    ex["rbsgs_256_stencil"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t}
+    # stream copy: achievable bandwidth
+    src = torch.empty(n * 8, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    its.stream_copy(src, dst)
+    t, _ = timed(lambda: its.stream_copy(src, dst), reps=20)
+    ex["stream_copy_gbs"] = 2 * src.numel() * 8 / t / 1e9
+    del src, dst
+    # BiCGStab on 192^3 upwind convection-diffusion (Peclet 10)
+    rp, col, val = inputs.convdiff7_csr(192)
+    n2, nnz2 = rp.size - 1, col.size
+    C = its.CSRMatrix.from_numpy(rp, col, val)
+    del rp, col, val
+    x2 = torch.from_numpy(inputs.uniform_vector(n2, 1)).cuda()
+    b2 = its.spmv(C, x2)
+    its.solve(C, b2, method="bicgstab", rtol=args.rtol, max_iter=2000)
+    reps = 10
+    t, (xb, info) = timed(lambda: its.solve(C, b2, method="bicgstab", rtol=args.rtol, max_iter=2000),
+                          reps=reps)
+    M2 = 12 * nnz2 + 4 * (n2 + 1)
+    ex["bicgstab_192_convdiff_csr"] = {"iters": info.iters, "restarts": info.restarts,
+                                       "s_per_solve": t, "iters_per_s": info.iters / t,
+                                       "solves_per_s": 1.0 / t,
+                                       "achieved_gbs": info.iters / t * (2 * M2 + 17 * 8 * n2) / 1e9,
+                                       "true_rel_res": info.true_rel_res}
+    log(f"extras: {json.dumps(ex)}")
+    return ex
+
+
+if __name__ == "__main__":
+    main()
