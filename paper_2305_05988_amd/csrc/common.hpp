@@ -13,7 +13,8 @@ namespace its {
 
 constexpr int kBlock = 256;             // threads per block: 4 wave64
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxGrid = 2048;          // cap on blocks of the streaming kernels
+constexpr int kGroup = 256;             // blocks per first-level reduction group
+constexpr int kMaxGrid = kGroup * kGroup;  // 65536 blocks: one 256-row tile each up to 16.7M rows
 constexpr int kMaxDots = 2;             // dot products reduced per kernel
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dealt round-robin
 
@@ -111,6 +112,7 @@ __device__ __forceinline__ Sched my_tiles(int64_t ntiles) {
   return {lo + slot, hi, per};
 }
 
+// Element-wise walk: body(i) for the thread's row of each of its tiles.
 template <class Body>
 __device__ __forceinline__ void for_rows(int32_t n, Body &&body) {
   const int64_t ntiles = (int64_t(n) + kBlock - 1) / kBlock;
@@ -118,6 +120,19 @@ __device__ __forceinline__ void for_rows(int32_t n, Body &&body) {
   for (int64_t t = s.begin; t < s.end; t += s.stride) {
     const int64_t i = t * kBlock + threadIdx.x;
     if (i < n) body(int32_t(i));
+  }
+}
+
+// Tile walk: body(r0, r1) for each of the block's tiles, called by every
+// thread of the block (the body may synchronise the block).
+template <class Body>
+__device__ __forceinline__ void for_tiles(int32_t n, Body &&body) {
+  const int64_t ntiles = (int64_t(n) + kBlock - 1) / kBlock;
+  const Sched s = my_tiles(ntiles);
+  for (int64_t t = s.begin; t < s.end; t += s.stride) {
+    const int32_t r0 = int32_t(t * kBlock);
+    const int32_t r1 = int32_t(min(int64_t(n), t * kBlock + kBlock));
+    body(r0, r1);
   }
 }
 
@@ -158,36 +173,70 @@ __device__ __forceinline__ void block_reduce(DD (&v)[ND]) {
   __syncthreads();
 }
 
-// Grid-wide reduction without a second launch: every block stores its
-// partial, and the block that arrives last (arrival counter) sums all G
-// partials in block order -- a fixed order, so the result does not depend on
-// scheduling -- and returns true in thread 0 with the totals in v.  The
-// counter is re-armed by that block.  Every block of the grid must call this.
+// Scratch of the grid-wide reductions: first-level partials (one per block
+// of a streaming pass), second-level partials (one per block of the finishing
+// kernel) and the finishing kernel's arrival counter.
+struct Reduce {
+  DD p1[kMaxDots][kMaxGrid];
+  DD p2[kMaxDots][kGroup];
+  uint32_t count;
+};
+
+// First level: the block's partial, stored by thread 0 with plain stores.
+// No fence and no atomic: the finishing kernel, launched after this one on
+// the same stream, sees the stores at the kernel boundary.
 template <int ND>
-__device__ __forceinline__ bool grid_reduce(DD (&v)[ND], DD *partials, uint32_t *counter) {
-  __shared__ int s_last;
-  const int G = gridDim.x;
+__device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R) {
   block_reduce<ND>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) partials[d * kMaxGrid + blockIdx.x] = v[d];
+    for (int d = 0; d < ND; ++d) R->p1[d][blockIdx.x] = v[d];
+  }
+}
+
+// Second level, inside the finishing kernel (one block per kGroup
+// first-level partials): each block sums its kGroup partials; with several
+// blocks, the last to arrive (counter) sums their results.  Partials are
+// always combined in index order, so the total does not depend on
+// scheduling.  Returns true in thread 0 of the block holding the total.
+template <int ND>
+__device__ __forceinline__ bool finish_reduce(DD (&v)[ND], Reduce *R, int G) {
+  __shared__ int s_last;
+  const int b = blockIdx.x, nb = gridDim.x;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const int j = b * kGroup + int(threadIdx.x);
+    v[d] = (j < G) ? R->p1[d][j] : DD{0.0, 0.0};
+  }
+  block_reduce<ND>(v);
+  if (nb == 1) return threadIdx.x == 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) R->p2[d][b] = v[d];
     __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
-    s_last = (prev == uint32_t(G - 1));
+    s_last = atomicAdd(&R->count, 1u) == uint32_t(nb - 1);
   }
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    DD t = {0.0, 0.0};
-    for (int j = threadIdx.x; j < G; j += kBlock) t = dd_add(t, partials[d * kMaxGrid + j]);
-    v[d] = t;
-  }
+  for (int d = 0; d < ND; ++d)
+    v[d] = (int(threadIdx.x) < nb) ? R->p2[d][threadIdx.x] : DD{0.0, 0.0};
   block_reduce<ND>(v);
-  if (threadIdx.x == 0) *counter = 0u;
+  if (threadIdx.x == 0) R->count = 0u;
   return threadIdx.x == 0;
 }
+
+// Finishing kernel: reduce the partials of the pass that ran before it and
+// apply Fin (the pass's scalar update) to the totals.
+template <int ND, class Fin>
+__global__ void __launch_bounds__(kBlock) k_finish(Reduce *R, int G, Fin fin) {
+  if (!fin.active()) return;
+  DD v[ND];
+  if (finish_reduce<ND>(v, R, G)) fin(v);
+}
+
+inline int finish_grid(int G) { return (G + kGroup - 1) / kGroup; }
 
 // ---------------------------------------------------------------- launch size
 

@@ -58,6 +58,9 @@ static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 namespace {
 
+constexpr int kClassFinish = 6;  // profile class of the finishing reductions
+constexpr int kClassOther = 7;   // setup and bookkeeping kernels
+
 struct Prof {
   bool on = false;
   its_result *res = nullptr;
@@ -109,7 +112,18 @@ struct Run {
     prof.end(s);
     return hipGetLastError();
   }
+  // The finishing kernel of a reducing pass that ran with G blocks.
+  template <int ND, class Fin>
+  hipError_t finish(Reduce *R, int G, Fin fin) {
+    return launch(kClassFinish, k_finish<ND, Fin>, finish_grid(G), R, G, fin);
+  }
 };
+
+#define FINISH(run, nd, R, G, fin)                                                              \
+  do {                                                                                        \
+    hipError_t e_ = (run).template finish<nd>(R, G, fin);                                     \
+    if (e_ != hipSuccess) return fail(ITS_E_HIP, std::string("launch: ") + hipGetErrorString(e_)); \
+  } while (0)
 
 #define LAUNCH(run, cls, kernel, grid, ...)                                                   \
   do {                                                                                        \
@@ -118,13 +132,13 @@ struct Run {
   } while (0)
 
 // ------------------------------------------------------------ workspace
-// [State main][State inner][partials: kMaxDots*kMaxGrid DD][vectors...],
-// every section 256-byte aligned.
+// [State main][State inner][Reduce scratch][vectors...], every section
+// 256-byte aligned.
 constexpr size_t kAlign = 256;
 inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t state = 0, state2 = 0, partials = 0, vec = 0, total = 0;
+  size_t state = 0, state2 = 0, reduce = 0, vec = 0, total = 0;
   int nvec64 = 0, nvec32 = 0;
 };
 
@@ -132,8 +146,8 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
   Layout L;
   L.state = 0;
   L.state2 = up(sizeof(State));
-  L.partials = L.state2 + up(sizeof(State));
-  L.vec = L.partials + up(sizeof(DD) * kMaxDots * kMaxGrid);
+  L.reduce = L.state2 + up(sizeof(State));
+  L.vec = L.reduce + up(sizeof(Reduce));
   switch (method) {
     case ITS_JACOBI: L.nvec64 = 1; break;
     case ITS_SGS: L.nvec64 = 0; break;
@@ -147,7 +161,7 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
 
 struct WS {
   State *st, *st2;
-  DD *partials;
+  Reduce *R;
   char *vec;
   size_t n;
   double *v64(int i) const { return reinterpret_cast<double *>(vec + size_t(i) * up(n * 8)); }
@@ -159,7 +173,7 @@ struct WS {
 WS carve(void *ws, const Layout &L, int64_t n) {
   char *b = static_cast<char *>(ws);
   return {reinterpret_cast<State *>(b + L.state), reinterpret_cast<State *>(b + L.state2),
-          reinterpret_cast<DD *>(b + L.partials), b + L.vec, size_t(n)};
+          reinterpret_cast<Reduce *>(b + L.reduce), b + L.vec, size_t(n)};
 }
 
 // ------------------------------------------------------------ operators
@@ -248,10 +262,12 @@ its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b,
                     double *r, State *host, double &bb, double &rr) {
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
-  LAUNCH(run, 7, k_reset_state, 1, w.st, 2);
-  LAUNCH(run, 7, k_dot, G, n, b, b, w.st, w.partials, 0, 0);
+  LAUNCH(run, kClassOther, k_reset, 1, w.st, 2, w.R);
+  LAUNCH(run, kClassOther, k_dot, G, n, b, b, w.R);
+  FINISH(run, 1, w.R, G, (FinDot{w.st, 0}));
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, 7, k_residual<decltype(op)>, G, op, b, x, r, w.st, w.partials, 1, 1);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, r, w.R);
+    FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
     return ITS_OK;
   });
   if (s != ITS_OK) return s;
@@ -271,7 +287,8 @@ its_status true_residual(Run &run, const its_matrix *A, const WS &w, const doubl
                          const double *x, State *host, double bb, its_result *res) {
   const int G = grid_for(A->n);
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, 7, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, w.st2, w.partials, 5, 2);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, w.R);
+    FINISH(run, 1, w.R, G, (FinDot{w.st2, 2}));
     return ITS_OK;
   });
   if (s != ITS_OK) return s;
@@ -294,7 +311,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
-    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
     HIP_TRY(hipStreamSynchronize(run.s));
     res->status = ITS_OK;
     return ITS_OK;
@@ -304,12 +321,14 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
-        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double *)r, (const double *)p, q, w.st, w.partials);
-        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, r, p, (const double *)q, w.st, w.partials, thr2, o->max_iter);
+        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double *)r, (const double *)p, q, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinCg1{w.st}));
+        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, r, p, (const double *)q, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinCg2{w.st, thr2, o->max_iter}));
         return ITS_OK;
       });
     });
@@ -341,7 +360,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
-    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
     HIP_TRY(hipStreamSynchronize(run.s));
     res->status = ITS_OK;
     return ITS_OK;
@@ -352,7 +371,8 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   for (;; ++outer) {
     if (outer > 0) {  // r = b - A x of the refined iterate
       s = with_op64(A, [&](auto op) -> its_status {
-        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, w.st, w.partials, 1, 1);
+        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, w.R);
+        FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
         return ITS_OK;
       });
       if (s != ITS_OK) return s;
@@ -364,18 +384,21 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     if (!std::isfinite(rr)) { res->status = ITS_BREAKDOWN; break; }
     if (outer == o->max_outer || inner_total >= o->max_iter) { res->status = ITS_NOT_CONVERGED; break; }
     const double rn = std::sqrt(rr);
-    LAUNCH(run, 3, k_ir_scale, G, n, (const double *)r, rh, d, w.st2, w.partials, rn);
+    LAUNCH(run, 3, k_ir_scale, G, n, (const double *)r, rh, d, w.R, rn);
+    FINISH(run, 1, w.R, G, (FinDot{w.st2, 1}));
     s = poll(run, w.st2, h);
     if (s != ITS_OK) return s;
     const double rho_i = h->dot[1];
     const double ithr2 = threshold2(o->inner_rtol, rho_i);
     const int64_t budget = o->max_iter - inner_total;
     if (!(rho_i <= ithr2)) {
-      LAUNCH(run, 7, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
+      LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
       s = with_op32(A, dt, [&](auto op) -> its_status {
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
-          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float *)rh, (const float *)p, q, w.st2, w.partials);
-          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rh, p, (const float *)q, w.st2, w.partials, ithr2, budget);
+          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float *)rh, (const float *)p, q, (const State *)w.st2, w.R);
+          FINISH(run, 1, w.R, G, (FinCg1{w.st2}));
+          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rh, p, (const float *)q, (const State *)w.st2, w.R);
+          FINISH(run, 1, w.R, G, (FinCg2{w.st2, ithr2, budget}));
           return ITS_OK;
         });
       });
@@ -408,7 +431,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
-    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
     HIP_TRY(hipStreamSynchronize(run.s));
     res->status = ITS_OK;
     return ITS_OK;
@@ -418,17 +441,21 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
-    LAUNCH(run, 7, k_bicg_init, G, n, (const double *)r, rs, w.st, w.partials, std::sqrt(rr));
+    LAUNCH(run, kClassOther, k_bicg_init, G, n, (const double *)r, rs, w.R, std::sqrt(rr));
+    FINISH(run, 1, w.R, G, (FinBicgInit{w.st}));
     const double rt2 = o->restart_tol * o->restart_tol;
     const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
     s = with_op64(A, [&](auto op) -> its_status {
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         const int a = int(j & 1), c = a ^ 1;
-        LAUNCH(run, 0, k_bicg_a<decltype(op)>, G, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], w.st, w.partials);
-        LAUNCH(run, 1, k_bicg_b<decltype(op)>, G, op, (const double *)r, (const double *)V[c], t, w.st, w.partials);
-        LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, w.st, w.partials, thr2, o->max_iter, rt2, paper);
+        LAUNCH(run, 0, k_bicg_a<decltype(op)>, G, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinBicgA{w.st}));
+        LAUNCH(run, 1, k_bicg_b<decltype(op)>, G, op, (const double *)r, (const double *)V[c], t, (const State *)w.st, w.R);
+        FINISH(run, 2, w.R, G, (FinBicgB{w.st}));
+        LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, (const State *)w.st, w.R);
+        FINISH(run, 2, w.R, G, (FinBicgC{w.st, thr2, o->max_iter, rt2, paper}));
         return ITS_OK;
       });
     });
@@ -459,18 +486,19 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
-    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
     HIP_TRY(hipStreamSynchronize(run.s));
     res->status = ITS_OK;
     return ITS_OK;
   }
   const double thr2 = threshold2(o->rtol, bb);
-  LAUNCH(run, 7, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
   // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
   s = with_op64(A, [&](auto op) -> its_status {
     return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
-      LAUNCH(run, 0, k_jacobi<decltype(op)>, G, op, b, (const double *)X[a], X[a ^ 1], w.st, w.partials, thr2, o->max_iter);
+      LAUNCH(run, 0, k_jacobi<decltype(op)>, G, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
+      FINISH(run, 1, w.R, G, (FinJacobi{w.st, thr2, o->max_iter}));
       return ITS_OK;
     });
   });
@@ -497,7 +525,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
-    LAUNCH(run, 7, k_fill, G, n, x, 0.0);
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
     HIP_TRY(hipStreamSynchronize(run.s));
     res->status = ITS_OK;
     return ITS_OK;
@@ -507,7 +535,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, 7, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   // Colour order of iteration j: forward 0..nc-1 then backward nc-1..0.  The
   // backward sweep's first colour repeats the forward sweep's last one on
   // unchanged inputs, and the next forward sweep's colour 0 repeats this
@@ -540,7 +568,8 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
           its_status e = sweep(c);
           if (e != ITS_OK) return e;
         }
-        LAUNCH(run, 1, k_gs_check<decltype(op)>, G, op, b, (const double *)x, w.st, w.partials, thr2, o->max_iter);
+        LAUNCH(run, 1, k_gs_check<decltype(op)>, G, op, b, (const double *)x, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinGs{w.st, thr2, o->max_iter}));
         return ITS_OK;
       });
     });
@@ -563,8 +592,8 @@ its_status check_diag(Run &run, its_matrix *A, const WS &w) {
   }
   if (A->diag_state != 0) return ITS_OK;
   uint32_t *bad = &w.st2->counter[7];
-  LAUNCH(run, 7, k_reset_state, 1, w.st2, 1);
-  LAUNCH(run, 7, k_csr_check, grid_for(A->n), int32_t(A->n), int32_t(A->nnz), A->rp, A->col, A->val, (int32_t)1, bad);
+  LAUNCH(run, kClassOther, k_reset, 1, w.st2, 1, w.R);
+  LAUNCH(run, kClassOther, k_csr_check, grid_for(A->n), int32_t(A->n), int32_t(A->nnz), A->rp, A->col, A->val, (int32_t)1, bad);
   its_status s = poll(run, w.st2, A->host_state);
   if (s != ITS_OK) return s;
   A->diag_state = A->host_state->counter[7] == 0 ? 1 : -1;
@@ -785,9 +814,7 @@ its_status its_spmv(const its_matrix *A, const double *x, double *y, void *strea
   return ITS_OK;
 }
 
-size_t its_dot_workspace_size(int64_t) {
-  return up(sizeof(State)) + up(sizeof(DD) * kMaxDots * kMaxGrid);
-}
+size_t its_dot_workspace_size(int64_t) { return up(sizeof(State)) + up(sizeof(Reduce)); }
 
 its_status its_dot(int64_t n, const double *x, const double *y, double *result, void *workspace,
                    size_t ws_bytes, void *stream) {
@@ -800,10 +827,12 @@ its_status its_dot(int64_t n, const double *x, const double *y, double *result, 
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(ITS_E_WORKSPACE, "workspace must be 256-byte aligned");
   State *st = static_cast<State *>(workspace);
-  DD *partials = reinterpret_cast<DD *>(static_cast<char *>(workspace) + up(sizeof(State)));
+  Reduce *R = reinterpret_cast<Reduce *>(static_cast<char *>(workspace) + up(sizeof(State)));
   hipStream_t s = S(stream);
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(kBlock), 0, s, st, 1);
-  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, int32_t(n), x, y, st, partials, 0, 0);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(kBlock), 0, s, st, 1, R);
+  const int G = grid_for(n);
+  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, s, int32_t(n), x, y, R);
+  hipLaunchKernelGGL((k_finish<1, FinDot>), dim3(finish_grid(G)), dim3(kBlock), 0, s, R, G, FinDot{st, 0});
   HIP_TRY(hipGetLastError());
   double v = 0.0;
   HIP_TRY(hipMemcpyAsync(&v, &st->dot[0], sizeof(double), hipMemcpyDeviceToHost, s));

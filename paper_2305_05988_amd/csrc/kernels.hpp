@@ -1,7 +1,7 @@
 // HIP kernels of the solver hot path.  Each iteration of a method is a short
 // sequence of fused streaming passes; the scalars of the method live in a
-// device State and are produced by the last block of each reducing pass, so
-// an iteration needs no host round trip.
+// device State and are produced by the block that finishes each pass's
+// grid reduction, so an iteration needs no host round trip.
 #pragma once
 
 #include "common.hpp"
@@ -11,12 +11,25 @@ namespace its {
 
 // ------------------------------------------------------------------ basics
 
-__global__ void k_reset_state(State *st, int nstates) {
-  // zero every field (counters included) of nstates consecutive States
+// Zero nstates consecutive States and the finishing kernel's counter.
+__global__ void k_reset(State *st, int nstates, Reduce *R) {
   uint32_t *w = reinterpret_cast<uint32_t *>(st);
   const int words = int(sizeof(State) / 4) * nstates;
   for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
+  if (threadIdx.x == 0) R->count = 0u;
 }
+
+// ------------------------------------------------------ scalar updates
+// Each reducing pass stores per-block partials; the finishing kernel that
+// follows it on the stream reduces them and applies one of these.
+
+// Stores a plain dot product into st->dot[out].
+struct FinDot {
+  State *st;
+  int out;
+  __device__ bool active() const { return true; }
+  __device__ void operator()(DD (&v)[1]) const { st->dot[out] = dd_round(v[0]); }
+};
 
 __global__ void k_begin(State *st, int32_t flag, double rho) {
   if (threadIdx.x != 0) return;
@@ -28,35 +41,48 @@ __global__ void k_begin(State *st, int32_t flag, double rho) {
   st->alpha = st->beta = st->omega = 0.0;
 }
 
-// Dot product x.y into st->dot[out].
+// Dot product x.y (finished by FinDot).
 __global__ void __launch_bounds__(kBlock) k_dot(int32_t n, const double *__restrict__ x,
-                                                const double *__restrict__ y, State *st,
-                                                DD *partials, int slot, int out) {
+                                                const double *__restrict__ y, Reduce *R) {
   Dot2 a;
   for_rows(n, [&](int32_t i) { a.add(x[i], y[i]); });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[slot])) st->dot[out] = dd_round(v[0]);
+  block_partial<1>(v, R);
 }
 
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_spmv(Op A, const double *__restrict__ x,
                                                  double *__restrict__ y) {
-  for_rows(A.n, [&](int32_t i) { y[i] = A.apply(i, [&](int32_t j) { return x[j]; }); });
+  __shared__ typename Op::Smem sm;
+  auto xj = [&](int32_t j) { return x[j]; };
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    double acc = 0.0;
+    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double a, double v) { acc = fma(a, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) y[i] = acc;
+  });
 }
 
-// r = b - A x (r may be null) and r.r into st->dot[out].
+// r = b - A x (r may be null) and r.r (finished by FinDot).
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *r,
-                                                     State *st, DD *partials, int slot, int out) {
+                                                     Reduce *R) {
+  __shared__ typename Op::Smem sm;
+  auto xj = [&](int32_t j) { return x[j]; };
   Dot2 a;
-  for_rows(A.n, [&](int32_t i) {
-    const double ri = b[i] - A.apply(i, [&](int32_t j) { return x[j]; });
-    if (r) r[i] = ri;
-    a.add(ri, ri);
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    double acc = 0.0;
+    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      const double ri = b[i] - acc;
+      if (r) r[i] = ri;
+      a.add(ri, ri);
+    }
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[slot])) st->dot[out] = dd_round(v[0]);
+  block_partial<1>(v, R);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill(int32_t n, double *x, double v) {
@@ -75,32 +101,43 @@ __global__ void __launch_bounds__(kBlock) k_fill(int32_t n, double *x, double v)
 template <class Op, class T>
 __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A, const T *__restrict__ r,
                                                      const T *__restrict__ p, T *__restrict__ q,
-                                                     State *st, DD *partials) {
+                                                     const State *st, Reduce *R) {
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
   const T beta = T(st->beta);
   auto pj = [&](int32_t j) -> T { return first ? r[j] : fmaT(beta, p[j], r[j]); };
   Dot2 a;
-  for_rows(A.n, [&](int32_t i) {
-    const T qi = A.apply(i, pj);
-    q[i] = qi;
-    a.add(double(pj(i)), double(qi));
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    T acc = T(0);
+    A.tile_entries(r0, r1, sm, pj, [&](int32_t, T av, T v) { acc = fmaT(av, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      q[i] = acc;
+      a.add(double(pj(i)), double(acc));
+    }
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[0])) {
+  block_partial<1>(v, R);
+}
+
+// alpha = rho / (p.q); p.q = 0 or non-finite is a breakdown.
+struct FinCg1 {
+  State *st;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
     const double pq = dd_round(v[0]);
     if (pq == 0.0 || !finite(pq))
       st->flag = kBreakdown;
     else
       st->alpha = st->rho / pq;
   }
-}
+};
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x, T *__restrict__ r,
                                                      T *__restrict__ p, const T *__restrict__ q,
-                                                     State *st, DD *partials, double thr2,
-                                                     int64_t max_iter) {
+                                                     const State *st, Reduce *R) {
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
   const T beta = T(st->beta), alpha = T(st->alpha);
@@ -115,7 +152,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
     a.add(double(ri), double(ri));
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[1])) {
+  block_partial<1>(v, R);
+}
+
+// rho' = r.r, one more iteration, beta = rho'/rho, convergence test.
+struct FinCg2 {
+  State *st;
+  double thr2;
+  int64_t max_iter;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
     const double rho_new = dd_round(v[0]);
     const int64_t k = st->k + 1;
     st->k = k;
@@ -128,7 +174,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
     else if (k >= max_iter)
       st->flag = kMaxIter;
   }
-}
+};
 
 // ------------------------------------------------------------------ Jacobi
 // One fused sweep: the residual of x_k (full chain) and x_{k+1} = (b - off)/d.
@@ -136,19 +182,40 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restrict__ b,
                                                    const double *__restrict__ xo,
-                                                   double *__restrict__ xn, State *st,
-                                                   DD *partials, double thr2, int64_t max_iter) {
+                                                   double *__restrict__ xn, const State *st,
+                                                   Reduce *R) {
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
+  auto xj = [&](int32_t j) { return xo[j]; };
   Dot2 a;
-  for_rows(A.n, [&](int32_t i) {
-    double full, off, diag;
-    A.relax(i, [&](int32_t j) { return xo[j]; }, full, off, diag);
-    const double ri = b[i] - full;
-    a.add(ri, ri);
-    xn[i] = (b[i] - off) / diag;
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    double full = 0.0, off = 0.0, diag = 0.0;
+    A.tile_entries(r0, r1, sm, xj, [&](int32_t j, double av, double v) {
+      full = fma(av, v, full);
+      if (j == i)
+        diag = av;
+      else
+        off = fma(av, v, off);
+    });
+    if (i < r1) {
+      const double ri = b[i] - full;
+      a.add(ri, ri);
+      xn[i] = (b[i] - off) / diag;
+    }
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[0])) {
+  block_partial<1>(v, R);
+}
+
+// The sweep's residual belongs to x_k: test it; if it fails, x_{k+1} is the
+// new iterate.
+struct FinJacobi {
+  State *st;
+  double thr2;
+  int64_t max_iter;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
     const double rr = dd_round(v[0]);
     const int64_t k = st->k;
     st->rho = rr;
@@ -161,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restric
     else
       st->k = k + 1;
   }
-}
+};
 
 // ------------------------------------------------------------ Gauss-Seidel
 // Half-sweep over the rows of one colour, in place.  Rows of one colour do
@@ -191,8 +258,11 @@ __global__ void __launch_bounds__(kBlock) k_gs_stencil(StencilOp<NPTS, double> A
     A.coords(i, ix, iy, iz);
     const int32_t c = (NPTS == 7) ? ((ix + iy + iz) & 1) : ((ix & 1) + 2 * (iy & 1) + 4 * (iz & 1));
     if (c != color) return;
-    double full, off;
-    A.template chain<true>(i, ix, iy, iz, [&](int32_t j) { return x[j]; }, full, off);
+    double off = 0.0;
+    A.row_entries_at(i, ix, iy, iz, [&](int32_t j) { return x[j]; },
+                     [&](int32_t j, double av, double v) {
+                       if (j != i) off = fma(av, v, off);
+                     });
     x[i] = (b[i] - off) / A.c[NPTS / 2];
   });
 }
@@ -200,16 +270,32 @@ __global__ void __launch_bounds__(kBlock) k_gs_stencil(StencilOp<NPTS, double> A
 // Residual of the iterate after a full symmetric iteration, and the test.
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restrict__ b,
-                                                     const double *__restrict__ x, State *st,
-                                                     DD *partials, double thr2, int64_t max_iter) {
+                                                     const double *__restrict__ x, const State *st,
+                                                     Reduce *R) {
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
+  auto xj = [&](int32_t j) { return x[j]; };
   Dot2 a;
-  for_rows(A.n, [&](int32_t i) {
-    const double ri = b[i] - A.apply(i, [&](int32_t j) { return x[j]; });
-    a.add(ri, ri);
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    double acc = 0.0;
+    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      const double ri = b[i] - acc;
+      a.add(ri, ri);
+    }
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[1])) {
+  block_partial<1>(v, R);
+}
+
+// Residual of x_{k+1} after a symmetric iteration, and the test.
+struct FinGs {
+  State *st;
+  double thr2;
+  int64_t max_iter;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
     const double rr = dd_round(v[0]);
     const int64_t k = st->k + 1;
     st->k = k;
@@ -221,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restr
     else if (k >= max_iter)
       st->flag = kMaxIter;
   }
-}
+};
 
 // --------------------------------------------------------------- BiCGStab
 // Algorithm 2's arithmetic in three fused passes per iteration:
@@ -233,8 +319,8 @@ __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restr
 // p and v are double-buffered (pass A gathers the old ones).
 
 __global__ void __launch_bounds__(kBlock) k_bicg_init(int32_t n, const double *__restrict__ r,
-                                                      double *__restrict__ rs, State *st,
-                                                      DD *partials, double rnorm) {
+                                                      double *__restrict__ rs, Reduce *R,
+                                                      double rnorm) {
   Dot2 a;
   for_rows(n, [&](int32_t i) {
     const double rsi = r[i] / rnorm;
@@ -242,15 +328,22 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(int32_t n, const double *_
     a.add(r[i], rsi);
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[3])) st->alpha_n = dd_round(v[0]);
+  block_partial<1>(v, R);
 }
+
+struct FinBicgInit {  // alpha_n = r.r'
+  State *st;
+  __device__ bool active() const { return true; }
+  __device__ void operator()(DD (&v)[1]) const { st->alpha_n = dd_round(v[0]); }
+};
 
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restrict__ r, double *rs,
                                                    const double *__restrict__ po,
                                                    const double *__restrict__ vo,
                                                    double *__restrict__ pn, double *__restrict__ vn,
-                                                   State *st, DD *partials) {
+                                                   const State *st, Reduce *R) {
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const bool plain = st->k == 0 || st->restart;
   const bool restart = st->restart;
@@ -260,21 +353,32 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
     return plain ? r[j] : fma(bet, fma(-om, vo[j], po[j]), r[j]);
   };
   Dot2 a;
-  for_rows(A.n, [&](int32_t i) {
-    const double vi = A.apply(i, pj);
-    pn[i] = pj(i);
-    vn[i] = vi;
-    double rsi;
-    if (restart) {
-      rsi = r[i] / rn;
-      rs[i] = rsi;
-    } else {
-      rsi = rs[i];
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    double acc = 0.0;
+    A.tile_entries(r0, r1, sm, pj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      pn[i] = pj(i);
+      vn[i] = acc;
+      double rsi;
+      if (restart) {
+        rsi = r[i] / rn;
+        rs[i] = rsi;
+      } else {
+        rsi = rs[i];
+      }
+      a.add(acc, rsi);
     }
-    a.add(vi, rsi);
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[0])) {
+  block_partial<1>(v, R);
+}
+
+// alpha_d = v.r', alpha = alpha_n / alpha_d; the restart (if any) is consumed.
+struct FinBicgA {
+  State *st;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
     const double ad = dd_round(v[0]);
     st->restart = 0;
     if (ad == 0.0 || !finite(ad)) {
@@ -284,39 +388,50 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
       st->alpha = st->alpha_n / ad;
     }
   }
-}
+};
 
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restrict__ r,
                                                    const double *__restrict__ v,
-                                                   double *__restrict__ t, State *st,
-                                                   DD *partials) {
+                                                   double *__restrict__ t, const State *st,
+                                                   Reduce *R) {
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const double alpha = st->alpha;
   auto sj = [&](int32_t j) -> double { return fma(-alpha, v[j], r[j]); };
   Dot2 a0, a1;
-  for_rows(A.n, [&](int32_t i) {
-    const double ti = A.apply(i, sj);
-    t[i] = ti;
-    a0.add(ti, sj(i));
-    a1.add(ti, ti);
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    double acc = 0.0;
+    A.tile_entries(r0, r1, sm, sj, [&](int32_t, double av, double x) { acc = fma(av, x, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      t[i] = acc;
+      a0.add(acc, sj(i));
+      a1.add(acc, acc);
+    }
   });
   DD d[2] = {a0.get(), a1.get()};
-  if (grid_reduce<2>(d, partials, &st->counter[1])) {
+  block_partial<2>(d, R);
+}
+
+// omega = (t.s) / (t.t), 0 if t.t = 0.
+struct FinBicgB {
+  State *st;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&d)[2]) const {
     const double ts = dd_round(d[0]), tt = dd_round(d[1]);
     st->ts = ts;
     st->tt = tt;
     st->omega = (tt == 0.0) ? 0.0 : ts / tt;
   }
-}
+};
 
 __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict__ x, double *r,
                                                    const double *__restrict__ rs,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ v,
-                                                   const double *__restrict__ t, State *st,
-                                                   DD *partials, double thr2, int64_t max_iter,
-                                                   double restart_tol2, int32_t paper_mode) {
+                                                   const double *__restrict__ t, const State *st,
+                                                   Reduce *R) {
   if (st->flag != kRunning) return;
   const double alpha = st->alpha, om = st->omega;
   const bool half = (om == 0.0);
@@ -336,7 +451,22 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
     a1.add(ri, ri);
   });
   DD d[2] = {a0.get(), a1.get()};
-  if (grid_reduce<2>(d, partials, &st->counter[2])) {
+  block_partial<2>(d, R);
+}
+
+// alpha_n' = r.r', beta = r.r; the restart test, then the convergence test
+// (in that order, as the restart count of the returned iterate includes a
+// restart decided in its last iteration).
+struct FinBicgC {
+  State *st;
+  double thr2;
+  int64_t max_iter;
+  double restart_tol2;
+  int32_t paper_mode;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&d)[2]) const {
+    const double om = st->omega;
+    const bool half = (om == 0.0);
     const double an = dd_round(d[0]), beta = dd_round(d[1]);
     const int64_t k = st->k + 1;
     st->k = k;
@@ -362,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
     else if (k >= max_iter)
       st->flag = kMaxIter;
   }
-}
+};
 
 // ------------------------------------------------- mixed-precision refinement
 // Outer step: rh = (float)(r/rn), d = 0, rh.rh; then (after the inner CG)
@@ -370,7 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
 
 __global__ void __launch_bounds__(kBlock) k_ir_scale(int32_t n, const double *__restrict__ r,
                                                      float *__restrict__ rh, float *__restrict__ d,
-                                                     State *st, DD *partials, double rn) {
+                                                     Reduce *R, double rn) {
   Dot2 a;
   for_rows(n, [&](int32_t i) {
     const float v = float(r[i] / rn);
@@ -379,7 +509,7 @@ __global__ void __launch_bounds__(kBlock) k_ir_scale(int32_t n, const double *__
     a.add(double(v), double(v));
   });
   DD v[1] = {a.get()};
-  if (grid_reduce<1>(v, partials, &st->counter[3])) st->dot[1] = dd_round(v[0]);
+  block_partial<1>(v, R);
 }
 
 __global__ void __launch_bounds__(kBlock) k_ir_update(int32_t n, double *__restrict__ x,
@@ -400,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_cast_f16(int64_t n, const double *sr
     dst[i] = static_cast<_Float16>(src[i]);
 }
 
-// Streaming copy, 16 bytes per lane per access.
+// Streaming copy, 16 bytes per lane.
 __global__ void __launch_bounds__(kBlock) k_copy(int64_t n, const double *__restrict__ src,
                                                  double *__restrict__ dst) {
   const int64_t n2 = n / 2;

@@ -4,11 +4,20 @@
 // can apply A to a vector it forms on the fly (p = r + beta p, s = r - alpha v)
 // without storing it first.  The SpMV of the paper (Sections 2.1-2.2) is
 // the chain with f(j) = x[j].
+//
+// Tiles: kernels walk the rows in tiles of kBlock rows, one row per thread,
+// through tile_entries(r0, r1, smem, fetch, consume): for the thread's row it
+// calls consume(j, a_ij, x_j) for every entry in stored order.  Entries are
+// handled in groups of kGather: all fetches of a group are issued before the
+// first consume, so a thread keeps up to kGather gathers in flight while the
+// chain itself stays strictly sequential.
 #pragma once
 
 #include "common.hpp"
 
 namespace its {
+
+constexpr int kGather = 8;
 
 __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
@@ -25,17 +34,75 @@ struct CsrOp {
   const V *__restrict__ val;
   int32_t n;
 
-  template <class F>
-  __device__ __forceinline__ T apply(int32_t i, F &&f) const {
-    T acc = T(0);
-    const int32_t e = rp[i + 1];
-    for (int32_t k = rp[i]; k < e; ++k) acc = fmaT(T(widen(val[k])), f(col[k]), acc);
-    return acc;
+  // A tile's entries are a contiguous slab of col/val.  It is copied to LDS
+  // in chunks of kCap entries with coalesced loads (the rows' own strided
+  // reads of col/val would touch every cache line once per entry), then each
+  // thread walks its row from LDS.  Rows longer than a chunk continue their
+  // chain across chunks, so any row length works.
+  static constexpr int kCap = 2048;
+  static constexpr int kLoads = kCap / kBlock;
+  struct Smem {
+    V val[kCap];
+    int32_t col[kCap];
+    int32_t rp[kBlock + 1];
+  };
+
+  template <class Fetch, class Consume>
+  __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &sm, Fetch &&fetch,
+                                               Consume &&consume) const {
+    const int t = threadIdx.x, nr = r1 - r0;
+    if (t < nr) sm.rp[t] = rp[r0 + t];
+    if (t == 0) sm.rp[nr] = rp[r1];
+    __syncthreads();
+    const int32_t k0 = sm.rp[0], k1 = sm.rp[nr];
+    const int32_t b = t < nr ? sm.rp[t] : 0, e = t < nr ? sm.rp[t + 1] : 0;
+    if (k1 == k0) {  // no entries: keep rp readers ahead of the next tile's writes
+      __syncthreads();
+      return;
+    }
+    for (int32_t c0 = k0; c0 < k1; c0 += kCap) {
+      const int32_t c1 = min(k1, c0 + kCap);
+      V vv[kLoads];
+      int32_t cc[kLoads];
+#pragma unroll
+      for (int u = 0; u < kLoads; ++u) {
+        const int32_t k = c0 + t + u * kBlock;
+        if (k < c1) {
+          vv[u] = val[k];
+          cc[u] = col[k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLoads; ++u) {
+        const int32_t k = c0 + t + u * kBlock;
+        if (k < c1) {
+          sm.val[k - c0] = vv[u];
+          sm.col[k - c0] = cc[u];
+        }
+      }
+      __syncthreads();
+      const int32_t kb = max(b, c0), ke = min(e, c1);
+      for (int32_t k = kb; k < ke; k += kGather) {
+        int32_t cj[kGather];
+        T aj[kGather], xj[kGather];
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) {
+          if (k + u < ke) {
+            cj[u] = sm.col[k + u - c0];
+            aj[u] = T(widen(sm.val[k + u - c0]));
+            xj[u] = fetch(cj[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGather; ++u)
+          if (k + u < ke) consume(cj[u], aj[u], xj[u]);
+      }
+      __syncthreads();
+    }
   }
 
-  // Relaxation helpers (Jacobi / Gauss-Seidel): the off-diagonal chain (the
-  // diagonal entry skipped), the full chain (b - full is the residual of the
-  // fetched vector) and the diagonal value.
+  // Row-at-a-time forms (direct global loads) for kernels that visit rows
+  // from a list rather than in tiles.
   template <class F>
   __device__ __forceinline__ void relax(int32_t i, F &&f, T &full, T &off, T &diag) const {
     full = T(0);
@@ -65,6 +132,8 @@ struct StencilOp {
   int32_t nx, ny, nz, n;
   T c[NPTS];
 
+  struct Smem {};
+
   __device__ __forceinline__ void coords(int32_t i, int32_t &ix, int32_t &iy, int32_t &iz) const {
     const int32_t t = i / nx;
     ix = i - t * nx;
@@ -72,57 +141,56 @@ struct StencilOp {
     iy = t - iz * ny;
   }
 
-  template <class F>
-  __device__ __forceinline__ T apply(int32_t i, F &&f) const {
-    int32_t ix, iy, iz;
-    coords(i, ix, iy, iz);
-    T full, off;
-    chain<false>(i, ix, iy, iz, f, full, off);
-    return full;
+  template <class Fetch, class Consume>
+  __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &, Fetch &&fetch,
+                                               Consume &&consume) const {
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) row_entries(i, fetch, consume);
   }
 
-  template <class F>
-  __device__ __forceinline__ void relax(int32_t i, F &&f, T &full, T &off, T &diag) const {
+  template <class Fetch, class Consume>
+  __device__ __forceinline__ void row_entries(int32_t i, Fetch &&fetch, Consume &&consume) const {
     int32_t ix, iy, iz;
     coords(i, ix, iy, iz);
-    chain<true>(i, ix, iy, iz, f, full, off);
-    diag = c[NPTS / 2];
+    row_entries_at(i, ix, iy, iz, fetch, consume);
   }
 
-  template <bool OFF, class F>
-  __device__ __forceinline__ void chain(int32_t i, int32_t ix, int32_t iy, int32_t iz, F &&f,
-                                        T &full, T &off) const {
+  template <class Fetch, class Consume>
+  __device__ __forceinline__ void row_entries_at(int32_t i, int32_t ix, int32_t iy, int32_t iz,
+                                                 Fetch &&fetch, Consume &&consume) const {
     const int32_t nxy = nx * ny;
-    full = T(0);
-    off = T(0);
     if constexpr (NPTS == 7) {
       const bool has[7] = {iz > 0, iy > 0, ix > 0, true, ix < nx - 1, iy < ny - 1, iz < nz - 1};
       const int32_t d[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+      T xv[7];
 #pragma unroll
-      for (int o = 0; o < 7; ++o) {
-        if (has[o]) {
-          const T xv = f(i + d[o]);
-          full = fmaT(c[o], xv, full);
-          if (OFF && o != 3) off = fmaT(c[o], xv, off);
-        }
-      }
+      for (int o = 0; o < 7; ++o)
+        if (has[o]) xv[o] = fetch(i + d[o]);
+#pragma unroll
+      for (int o = 0; o < 7; ++o)
+        if (has[o]) consume(i + d[o], c[o], xv[o]);
     } else {
 #pragma unroll
       for (int dk = -1; dk <= 1; ++dk) {
+        // one plane (9 entries) of gathers in flight at a time
+        T xv[9];
+        bool in[9];
 #pragma unroll
-        for (int dj = -1; dj <= 1; ++dj) {
+        for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
           for (int di = -1; di <= 1; ++di) {
-            const int o = (dk + 1) * 9 + (dj + 1) * 3 + (di + 1);
-            const bool in = (iz + dk >= 0) && (iz + dk < nz) && (iy + dj >= 0) && (iy + dj < ny) &&
-                            (ix + di >= 0) && (ix + di < nx);
-            if (in) {
-              const T xv = f(i + dk * nxy + dj * nx + di);
-              full = fmaT(c[o], xv, full);
-              if (OFF && o != 13) off = fmaT(c[o], xv, off);
-            }
+            const int u = (dj + 1) * 3 + (di + 1);
+            in[u] = (iz + dk >= 0) && (iz + dk < nz) && (iy + dj >= 0) && (iy + dj < ny) &&
+                    (ix + di >= 0) && (ix + di < nx);
+            if (in[u]) xv[u] = fetch(i + dk * nxy + dj * nx + di);
           }
-        }
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 1; ++di) {
+            const int u = (dj + 1) * 3 + (di + 1);
+            if (in[u]) consume(i + dk * nxy + dj * nx + di, c[(dk + 1) * 9 + u], xv[u]);
+          }
       }
     }
   }
