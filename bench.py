@@ -30,6 +30,10 @@ METRIC = "CG iters/s + achieved HBM GB/s, 256^3 Poisson; mixed-prec vs FP64 at 1
 KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/kernels.hpp", "paper_2305_05988_amd/csrc/common.hpp",
                   "paper_2305_05988_amd/csrc/ops.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_pass1_poisson256_traffic.txt")
+# Inside the timed region every PROFILE_EVERY-th launch of each kernel is
+# bracketed by HIP events: enough samples for the per-launch average, few
+# enough markers not to perturb the iteration rate.
+PROFILE_EVERY = 8
 
 
 def log(*a):
@@ -93,6 +97,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="profiling: solve with rtol=0 for exactly this many iterations")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
@@ -109,6 +117,13 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        its.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: {src.numel() * 8} bytes read, {dst.numel() * 8} bytes written")
+        del src, dst
     N = args.n
     t0 = time.perf_counter()
     rp, col, val = inputs.poisson7_csr(N)
@@ -127,16 +142,18 @@ def main():
     bytes_pass2 = 7 * V      # read x, r, p, q; write x, r, p
 
     opts = dict(method="cg", rtol=args.rtol, max_iter=20000)
+    if args.fixed_iters:
+        opts = dict(method="cg", rtol=0.0, max_iter=args.fixed_iters)
     ws = torch.empty(its.api.workspace_bytes(A, **opts), dtype=torch.uint8, device="cuda")
     for _ in range(args.warmup):
-        x, info = its.solve(A, b, workspace=ws, profile=True, **opts)
+        x, info = its.solve(A, b, workspace=ws, profile=PROFILE_EVERY, **opts)
     torch.cuda.synchronize()
     iters = 0
     ms1 = ms2 = 0.0
     l1 = l2 = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x, info = its.solve(A, b, workspace=ws, profile=True, **opts)
+        x, info = its.solve(A, b, workspace=ws, profile=PROFILE_EVERY, **opts)
         iters += info.iters
         ms1 += info.kernel_ms[0]
         ms2 += info.kernel_ms[1]
@@ -144,7 +161,7 @@ def main():
         l2 += info.kernel_launches[1]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    assert info.status == "ok", info
+    assert info.status == ("not_converged" if args.fixed_iters else "ok"), info
     its_per_s = iters / dt
     avg1 = ms1 / max(l1, 1) * 1e-3
     avg2 = ms2 / max(l2, 1) * 1e-3

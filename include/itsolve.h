@@ -64,8 +64,9 @@ typedef struct {
                            (its_csr_set_lowp) and FP32 vectors */
   double inner_rtol;    /* IR: relative tolerance of each inner solve */
   int64_t max_outer;    /* IR: cap on refinement steps */
-  int32_t profile;      /* 1: time every kernel launch with HIP events and
-                           report per-class totals in its_result */
+  int32_t profile;      /* 0: off.  k >= 1: time every k-th launch of each
+                           kernel class with HIP events on the stream and
+                           report the timed launches in its_result */
   int32_t reserved;
 } its_options;
 
@@ -78,7 +79,8 @@ typedef struct {
   int64_t inner_iters;  /* IR: total inner CG iterations */
   double rel_res;       /* recursive ||r_k|| / ||b|| at exit */
   double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit */
-  /* profile != 0 only: summed duration and launch count per kernel class.
+  /* profile != 0 only: summed duration and count of the timed launches per
+     kernel class (6 = finishing reductions, 7 = setup and bookkeeping).
      CG: 0 = SpMV+dot pass, 1 = update+dot pass.  BiCGStab: 0 = A p pass,
      1 = A s pass, 2 = update pass.  Jacobi: 0 = sweep.  SGS: 0 = colour
      half-sweeps, 1 = residual.  IR: 0/1 = inner passes as CG, 2 = outer

@@ -186,7 +186,7 @@ def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mo
     o.inner_rtol = inner_rtol
     o.max_outer = max_outer
     o.check_every = check_every
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)
     return o
 
 

@@ -90,6 +90,23 @@ __device__ __forceinline__ double dd_round(DD v) { return v.hi + v.lo; }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// Streaming (non-temporal) accesses for data used once per pass: the matrix
+// arrays and the vectors a pass reads or writes only for its own rows.  They
+// keep L2 for the vector entries that neighbouring rows gather, and leave
+// little dirty data behind.
+template <class T>
+__device__ __forceinline__ T ld_nt(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ __half ld_nt(const __half *p) {
+  const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+  return __builtin_bit_cast(__half, b);
+}
+template <class T>
+__device__ __forceinline__ void st_nt(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
 

@@ -62,34 +62,38 @@ constexpr int kClassFinish = 6;  // profile class of the finishing reductions
 constexpr int kClassOther = 7;   // setup and bookkeeping kernels
 
 struct Prof {
-  bool on = false;
+  int every = 0;  // 0: off; k: time every k-th launch of each class
   its_result *res = nullptr;
   std::vector<hipEvent_t> ev;
   std::vector<int> cls;
+  int64_t seen[ITS_MAX_KERNEL_CLASSES] = {};
   size_t used = 0;
+  bool open = false;
   ~Prof() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
   void begin(int c, hipStream_t s) {
-    if (!on) return;
+    open = false;
+    if (every <= 0 || (seen[c]++ % every) != 0) return;
     while (ev.size() < used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) {
-        on = false;
+        every = 0;
         return;
       }
       ev.push_back(e);
     }
     (void)hipEventRecord(ev[used], s);
     cls.push_back(c);
+    open = true;
   }
   void end(hipStream_t s) {
-    if (!on) return;
+    if (!open) return;
     (void)hipEventRecord(ev[used + 1], s);
     used += 2;
+    open = false;
   }
   void flush() {  // after a stream synchronisation
-    if (!on) return;
     for (size_t p = 0; p < cls.size(); ++p) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]) == hipSuccess) {
@@ -611,6 +615,7 @@ bool options_ok(const its_options *o, std::string &why) {
   if (o->inner_dtype != ITS_F64 && o->method != ITS_CG) { why = "mixed precision is for CG only"; return false; }
   if (!(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol)) { why = "inner_rtol must be finite and >= 0"; return false; }
   if (o->max_outer < 0) { why = "max_outer must be >= 0"; return false; }
+  if (o->profile < 0) { why = "profile must be >= 0"; return false; }
   return true;
 }
 
@@ -870,7 +875,7 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
   }
   Run run;
   run.s = S(stream);
-  run.prof.on = o->profile != 0;
+  run.prof.every = o->profile;
   run.prof.res = res;
   const WS w = carve(workspace, L, A->n);
   if (o->method == ITS_JACOBI || o->method == ITS_SGS) {

@@ -45,7 +45,7 @@ __global__ void k_begin(State *st, int32_t flag, double rho) {
 __global__ void __launch_bounds__(kBlock) k_dot(int32_t n, const double *__restrict__ x,
                                                 const double *__restrict__ y, Reduce *R) {
   Dot2 a;
-  for_rows(n, [&](int32_t i) { a.add(x[i], y[i]); });
+  for_rows(n, [&](int32_t i) { a.add(ld_nt(x + i), ld_nt(y + i)); });
   DD v[1] = {a.get()};
   block_partial<1>(v, R);
 }
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Op A, const double *__restrict_
     double acc = 0.0;
     A.tile_entries(r0, r1, sm, xj, [&](int32_t, double a, double v) { acc = fma(a, v, acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) y[i] = acc;
+    if (i < r1) st_nt(y + i, acc);
   });
 }
 
@@ -76,8 +76,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restr
     A.tile_entries(r0, r1, sm, xj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
-      const double ri = b[i] - acc;
-      if (r) r[i] = ri;
+      const double ri = ld_nt(b + i) - acc;
+      if (r) st_nt(r + i, ri);
       a.add(ri, ri);
     }
   });
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A, const T *__restrict__
     A.tile_entries(r0, r1, sm, pj, [&](int32_t, T av, T v) { acc = fmaT(av, v, acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
-      q[i] = acc;
+      st_nt(q + i, acc);
       a.add(double(pj(i)), double(acc));
     }
   });
@@ -143,12 +143,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   const T beta = T(st->beta), alpha = T(st->alpha);
   Dot2 a;
   for_rows(n, [&](int32_t i) {
-    const T r0 = r[i];
-    const T pi = first ? r0 : fmaT(beta, p[i], r0);
-    p[i] = pi;
-    x[i] = fmaT(alpha, pi, x[i]);
-    const T ri = fmaT(-alpha, q[i], r0);
-    r[i] = ri;
+    const T r0 = ld_nt(r + i);
+    const T pi = first ? r0 : fmaT(beta, ld_nt(p + i), r0);
+    const T xi = ld_nt(x + i);
+    const T qi = ld_nt(q + i);
+    st_nt(p + i, pi);
+    st_nt(x + i, fmaT(alpha, pi, xi));
+    const T ri = fmaT(-alpha, qi, r0);
+    st_nt(r + i, ri);
     a.add(double(ri), double(ri));
   });
   DD v[1] = {a.get()};
@@ -199,9 +201,10 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restric
         off = fma(av, v, off);
     });
     if (i < r1) {
-      const double ri = b[i] - full;
+      const double bi = ld_nt(b + i);
+      const double ri = bi - full;
       a.add(ri, ri);
-      xn[i] = (b[i] - off) / diag;
+      st_nt(xn + i, (bi - off) / diag);
     }
   });
   DD v[1] = {a.get()};
@@ -358,8 +361,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
     A.tile_entries(r0, r1, sm, pj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
-      pn[i] = pj(i);
-      vn[i] = acc;
+      st_nt(pn + i, pj(i));
+      st_nt(vn + i, acc);
       double rsi;
       if (restart) {
         rsi = r[i] / rn;
@@ -405,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restric
     A.tile_entries(r0, r1, sm, sj, [&](int32_t, double av, double x) { acc = fma(av, x, acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
-      t[i] = acc;
+      st_nt(t + i, acc);
       a0.add(acc, sj(i));
       a1.add(acc, acc);
     }
@@ -437,17 +440,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
   const bool half = (om == 0.0);
   Dot2 a0, a1;
   for_rows(n, [&](int32_t i) {
-    const double si = fma(-alpha, v[i], r[i]);
+    const double si = fma(-alpha, ld_nt(v + i), ld_nt(r + i));
+    const double xi = ld_nt(x + i), pi = ld_nt(p + i), rsi = ld_nt(rs + i);
     double ri;
     if (half) {
-      x[i] = fma(alpha, p[i], x[i]);
+      st_nt(x + i, fma(alpha, pi, xi));
       ri = si;
     } else {
-      x[i] = fma(om, si, fma(alpha, p[i], x[i]));
-      ri = fma(-om, t[i], si);
+      st_nt(x + i, fma(om, si, fma(alpha, pi, xi)));
+      ri = fma(-om, ld_nt(t + i), si);
     }
-    r[i] = ri;
-    a0.add(ri, rs[i]);
+    st_nt(r + i, ri);
+    a0.add(ri, rsi);
     a1.add(ri, ri);
   });
   DD d[2] = {a0.get(), a1.get()};
@@ -514,7 +518,7 @@ __global__ void __launch_bounds__(kBlock) k_ir_scale(int32_t n, const double *__
 
 __global__ void __launch_bounds__(kBlock) k_ir_update(int32_t n, double *__restrict__ x,
                                                       const float *__restrict__ d, double rn) {
-  for_rows(n, [&](int32_t i) { x[i] = fma(rn, double(d[i]), x[i]); });
+  for_rows(n, [&](int32_t i) { st_nt(x + i, fma(rn, double(ld_nt(d + i)), ld_nt(x + i))); });
 }
 
 // ----------------------------------------------------------------- utilities

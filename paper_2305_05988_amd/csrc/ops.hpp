@@ -51,8 +51,8 @@ struct CsrOp {
   __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &sm, Fetch &&fetch,
                                                Consume &&consume) const {
     const int t = threadIdx.x, nr = r1 - r0;
-    if (t < nr) sm.rp[t] = rp[r0 + t];
-    if (t == 0) sm.rp[nr] = rp[r1];
+    if (t < nr) sm.rp[t] = ld_nt(rp + r0 + t);
+    if (t == 0) sm.rp[nr] = ld_nt(rp + r1);
     __syncthreads();
     const int32_t k0 = sm.rp[0], k1 = sm.rp[nr];
     const int32_t b = t < nr ? sm.rp[t] : 0, e = t < nr ? sm.rp[t + 1] : 0;
@@ -68,8 +68,8 @@ struct CsrOp {
       for (int u = 0; u < kLoads; ++u) {
         const int32_t k = c0 + t + u * kBlock;
         if (k < c1) {
-          vv[u] = val[k];
-          cc[u] = col[k];
+          vv[u] = ld_nt(val + k);
+          cc[u] = ld_nt(col + k);
         }
       }
 #pragma unroll
