@@ -98,7 +98,8 @@ void its_default_options(its_options *opts /* host, out */);
 /* CSR matrix (Section 2.2).  row_ptr: n+1 int32 (row_ptr[0] = 0,
    nondecreasing, row_ptr[n] = nnz); col: nnz int32 in [0, n); val: nnz
    float64.  Rows are applied in stored order (store columns ascending).
-   All three are device pointers, borrowed.  Requires nnz < 2^31.
+   All three are device pointers, borrowed; col and val 16-byte aligned
+   (fresh device allocations are).  Requires nnz < 2^31.
    Structure is not validated here (use its_csr_validate). */
 its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                           const double *val, its_matrix **out /* host, out */);
@@ -111,7 +112,7 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream);
 
 /* Attaches low-precision copies of the CSR values (same structure) for the
    mixed-precision CG: dtype ITS_F32 (float) or ITS_F16 (IEEE half).  Device
-   pointer, borrowed.  One array per dtype may be attached. */
+   pointer, borrowed, 16-byte aligned.  One array per dtype may be attached. */
 its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
 
 /* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 2.4:

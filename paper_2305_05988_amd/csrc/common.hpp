@@ -90,6 +90,13 @@ __device__ __forceinline__ double dd_round(DD v) { return v.hi + v.lo; }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// Two-element vectors for interleaved pairs (one 16- or 8-byte access).
+typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+template <class T> struct Pair;
+template <> struct Pair<double> { using type = double2_t; };
+template <> struct Pair<float> { using type = float2_t; };
+
 // Streaming (non-temporal) accesses for data used once per pass: the matrix
 // arrays and the vectors a pass reads or writes only for its own rows.  They
 // keep L2 for the vector entries that neighbouring rows gather, and leave
@@ -191,17 +198,17 @@ __device__ __forceinline__ void block_reduce(DD (&v)[ND]) {
 }
 
 // Scratch of the grid-wide reductions: first-level partials (one per block
-// of a streaming pass), second-level partials (one per block of the finishing
-// kernel) and the finishing kernel's arrival counter.
+// of a streaming pass) and second-level partials (one per group of kGroup
+// first-level partials).
 struct Reduce {
   DD p1[kMaxDots][kMaxGrid];
   DD p2[kMaxDots][kGroup];
-  uint32_t count;
+  uint32_t count;  // unused; kept for layout stability
 };
 
 // First level: the block's partial, stored by thread 0 with plain stores.
-// No fence and no atomic: the finishing kernel, launched after this one on
-// the same stream, sees the stores at the kernel boundary.
+// No fence and no atomic: the finishing kernels, launched after this one on
+// the same stream, see the stores at the kernel boundary.
 template <int ND>
 __device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R) {
   block_reduce<ND>(v);
@@ -211,46 +218,39 @@ __device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R) {
   }
 }
 
-// Second level, inside the finishing kernel (one block per kGroup
-// first-level partials): each block sums its kGroup partials; with several
-// blocks, the last to arrive (counter) sums their results.  Partials are
-// always combined in index order, so the total does not depend on
-// scheduling.  Returns true in thread 0 of the block holding the total.
+// The partials of a pass with G blocks are finished by one kernel when
+// G <= kGroup, else by two: k_finish_group (block b sums first-level
+// partials kGroup*b .. kGroup*b+kGroup-1 into p2[b]) and k_finish_final over
+// the group sums.  Partials are combined in index order at both levels, so
+// the total does not depend on scheduling, and no fence is needed: each
+// level reads what the previous kernel stored.  (An in-kernel "last block"
+// needs agent-scope fences, which on this GPU write back and invalidate L2
+// and cost more than the extra launch.)
 template <int ND>
-__device__ __forceinline__ bool finish_reduce(DD (&v)[ND], Reduce *R, int G) {
-  __shared__ int s_last;
-  const int b = blockIdx.x, nb = gridDim.x;
+__global__ void __launch_bounds__(kBlock) k_finish_group(Reduce *R, int G) {
+  DD v[ND];
+  const int j = blockIdx.x * kGroup + int(threadIdx.x);
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    const int j = b * kGroup + int(threadIdx.x);
-    v[d] = (j < G) ? R->p1[d][j] : DD{0.0, 0.0};
-  }
+  for (int d = 0; d < ND; ++d) v[d] = (j < G) ? R->p1[d][j] : DD{0.0, 0.0};
   block_reduce<ND>(v);
-  if (nb == 1) return threadIdx.x == 0;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) R->p2[d][b] = v[d];
-    __threadfence();
-    s_last = atomicAdd(&R->count, 1u) == uint32_t(nb - 1);
+    for (int d = 0; d < ND; ++d) R->p2[d][blockIdx.x] = v[d];
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-#pragma unroll
-  for (int d = 0; d < ND; ++d)
-    v[d] = (int(threadIdx.x) < nb) ? R->p2[d][threadIdx.x] : DD{0.0, 0.0};
-  block_reduce<ND>(v);
-  if (threadIdx.x == 0) R->count = 0u;
-  return threadIdx.x == 0;
 }
 
-// Finishing kernel: reduce the partials of the pass that ran before it and
-// apply Fin (the pass's scalar update) to the totals.
+// Single block: reduce `count` partials (from p1 if `level` is 1, else p2)
+// and apply Fin (the pass's scalar update) to the totals.
 template <int ND, class Fin>
-__global__ void __launch_bounds__(kBlock) k_finish(Reduce *R, int G, Fin fin) {
+__global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, int level, Fin fin) {
   if (!fin.active()) return;
   DD v[ND];
-  if (finish_reduce<ND>(v, R, G)) fin(v);
+  const int j = int(threadIdx.x);
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+    v[d] = (j < count) ? (level == 1 ? R->p1[d][j] : R->p2[d][j]) : DD{0.0, 0.0};
+  block_reduce<ND>(v);
+  if (threadIdx.x == 0) fin(v);
 }
 
 inline int finish_grid(int G) { return (G + kGroup - 1) / kGroup; }

@@ -116,10 +116,14 @@ struct Run {
     prof.end(s);
     return hipGetLastError();
   }
-  // The finishing kernel of a reducing pass that ran with G blocks.
+  // The finishing kernel(s) of a reducing pass that ran with G blocks.
   template <int ND, class Fin>
   hipError_t finish(Reduce *R, int G, Fin fin) {
-    return launch(kClassFinish, k_finish<ND, Fin>, finish_grid(G), R, G, fin);
+    const int nb = finish_grid(G);
+    if (nb == 1) return launch(kClassFinish, k_finish_final<ND, Fin>, 1, R, G, 1, fin);
+    hipError_t e = launch(kClassFinish, k_finish_group<ND>, nb, R, G);
+    if (e != hipSuccess) return e;
+    return launch(kClassFinish, k_finish_final<ND, Fin>, 1, R, nb, 2, fin);
   }
 };
 
@@ -142,42 +146,58 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t state = 0, state2 = 0, reduce = 0, vec = 0, total = 0;
-  int nvec64 = 0, nvec32 = 0;
+  size_t state = 0, state2 = 0, reduce = 0, total = 0;
+  size_t off[8] = {};  // offsets of the method's vector regions
+  int nreg = 0;
 };
 
+// Vector regions per method (bytes per row):
+//   Jacobi   : x ping-pong buffer (8)
+//   CG       : {r, p} interleaved pairs (16), q (8)
+//   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
+//   BiCGStab : r, r', p0, p1, v0, v1, t (8 each)
 Layout layout_for(int64_t n, int method, int inner_dtype) {
   Layout L;
   L.state = 0;
   L.state2 = up(sizeof(State));
   L.reduce = L.state2 + up(sizeof(State));
-  L.vec = L.reduce + up(sizeof(Reduce));
+  size_t at = L.reduce + up(sizeof(Reduce));
+  int per[8] = {};
   switch (method) {
-    case ITS_JACOBI: L.nvec64 = 1; break;
-    case ITS_SGS: L.nvec64 = 0; break;
-    case ITS_CG: L.nvec64 = (inner_dtype == ITS_F64) ? 3 : 1; L.nvec32 = (inner_dtype == ITS_F64) ? 0 : 4; break;
-    case ITS_BICGSTAB: L.nvec64 = 7; break;
+    case ITS_JACOBI: L.nreg = 1; per[0] = 8; break;
+    case ITS_SGS: L.nreg = 0; break;
+    case ITS_CG:
+      if (inner_dtype == ITS_F64) {
+        L.nreg = 2; per[0] = 16; per[1] = 8;
+      } else {
+        L.nreg = 4; per[0] = 8; per[1] = 8; per[2] = 4; per[3] = 4;
+      }
+      break;
+    case ITS_BICGSTAB: L.nreg = 7; for (int i = 0; i < 7; ++i) per[i] = 8; break;
     default: break;
   }
-  L.total = L.vec + size_t(L.nvec64) * up(size_t(n) * 8) + size_t(L.nvec32) * up(size_t(n) * 4);
+  for (int i = 0; i < L.nreg; ++i) {
+    L.off[i] = at;
+    at += up(size_t(n) * size_t(per[i]));
+  }
+  L.total = at;
   return L;
 }
 
 struct WS {
   State *st, *st2;
   Reduce *R;
-  char *vec;
-  size_t n;
-  double *v64(int i) const { return reinterpret_cast<double *>(vec + size_t(i) * up(n * 8)); }
-  float *v32(int nvec64, int i) const {
-    return reinterpret_cast<float *>(vec + size_t(nvec64) * up(n * 8) + size_t(i) * up(n * 4));
-  }
+  char *base;
+  Layout L;
+  template <class T>
+  T *reg(int i) const { return reinterpret_cast<T *>(base + L.off[i]); }
+  double *v64(int i) const { return reg<double>(i); }
 };
 
-WS carve(void *ws, const Layout &L, int64_t n) {
+WS carve(void *ws, const Layout &L, int64_t) {
   char *b = static_cast<char *>(ws);
   return {reinterpret_cast<State *>(b + L.state), reinterpret_cast<State *>(b + L.state2),
-          reinterpret_cast<Reduce *>(b + L.reduce), b + L.vec, size_t(n)};
+          reinterpret_cast<Reduce *>(b + L.reduce), b, L};
 }
 
 // ------------------------------------------------------------ operators
@@ -263,14 +283,14 @@ its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, in
 // Common prologue: zero the States, b.b, r0 = b - A x0 (stored in r if
 // non-null) and r0.r0.  Returns bb and rr0 through `host`.
 its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b, const double *x,
-                    double *r, State *host, double &bb, double &rr) {
+                    double *r, int rstride, State *host, double &bb, double &rr) {
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
   LAUNCH(run, kClassOther, k_reset, 1, w.st, 2, w.R);
   LAUNCH(run, kClassOther, k_dot, G, n, b, b, w.R);
   FINISH(run, 1, w.R, G, (FinDot{w.st, 0}));
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, r, w.R);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, r, rstride, w.R);
     FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
     return ITS_OK;
   });
@@ -291,7 +311,7 @@ its_status true_residual(Run &run, const its_matrix *A, const WS &w, const doubl
                          const double *x, State *host, double bb, its_result *res) {
   const int G = grid_for(A->n);
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, w.R);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, 1, w.R);
     FINISH(run, 1, w.R, G, (FinDot{w.st2, 2}));
     return ITS_OK;
   });
@@ -309,9 +329,10 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
-  double *r = w.v64(0), *p = w.v64(1), *q = w.v64(2);
+  double2_t *rp = w.reg<double2_t>(0);  // {r, p} pairs
+  double *q = w.v64(1);
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, reinterpret_cast<double *>(rp), 2, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -329,9 +350,9 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
-        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double *)r, (const double *)p, q, (const State *)w.st, w.R);
+        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCg1{w.st}));
-        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, r, p, (const double *)q, (const State *)w.st, w.R);
+        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, rp, (const double *)q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCg2{w.st, thr2, o->max_iter}));
         return ITS_OK;
       });
@@ -358,9 +379,10 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   if (A->kind == kCsr && ((dt == ITS_F32 && !A->val32) || (dt == ITS_F16 && !A->val16)))
     return fail(ITS_E_INVALID, "mixed precision needs its_csr_set_lowp values of that dtype");
   double *r = w.v64(0);
-  float *rh = w.v32(1, 0), *p = w.v32(1, 1), *q = w.v32(1, 2), *d = w.v32(1, 3);
+  float2_t *rhp = w.reg<float2_t>(1);  // inner {r, p} pairs
+  float *q = w.reg<float>(2), *d = w.reg<float>(3);
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, r, 1, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -375,7 +397,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   for (;; ++outer) {
     if (outer > 0) {  // r = b - A x of the refined iterate
       s = with_op64(A, [&](auto op) -> its_status {
-        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, w.R);
+        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, 1, w.R);
         FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
         return ITS_OK;
       });
@@ -388,7 +410,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     if (!std::isfinite(rr)) { res->status = ITS_BREAKDOWN; break; }
     if (outer == o->max_outer || inner_total >= o->max_iter) { res->status = ITS_NOT_CONVERGED; break; }
     const double rn = std::sqrt(rr);
-    LAUNCH(run, 3, k_ir_scale, G, n, (const double *)r, rh, d, w.R, rn);
+    LAUNCH(run, 3, k_ir_scale, G, n, (const double *)r, reinterpret_cast<float *>(rhp), d, w.R, rn);
     FINISH(run, 1, w.R, G, (FinDot{w.st2, 1}));
     s = poll(run, w.st2, h);
     if (s != ITS_OK) return s;
@@ -399,9 +421,9 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
       LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
       s = with_op32(A, dt, [&](auto op) -> its_status {
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
-          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float *)rh, (const float *)p, q, (const State *)w.st2, w.R);
+          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, G, (FinCg1{w.st2}));
-          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rh, p, (const float *)q, (const State *)w.st2, w.R);
+          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, G, (FinCg2{w.st2, ithr2, budget}));
           return ITS_OK;
         });
@@ -431,7 +453,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   double *r = w.v64(0), *rs = w.v64(1), *P[2] = {w.v64(2), w.v64(3)}, *V[2] = {w.v64(4), w.v64(5)},
          *t = w.v64(6);
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, r, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, r, 1, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -486,7 +508,7 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
   const int G = grid_for(n);
   double *X[2] = {x, w.v64(0)};
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, nullptr, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, nullptr, 1, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -525,7 +547,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   const int G = grid_for(n);
   const int nc = A->kind == kCsr ? A->ncolors : (A->kind == kSten7 ? 2 : 8);
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, nullptr, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, nullptr, 1, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -677,6 +699,8 @@ its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const 
   if (n >= (int64_t(1) << 31) - 1 || nnz >= (int64_t(1) << 31))
     return fail(ITS_E_UNSUPPORTED, "n and nnz must be below 2^31");
   if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(ITS_E_INVALID, "null CSR array");
+  if ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(val)) % 16)
+    return fail(ITS_E_INVALID, "col and val must be 16-byte aligned");
   its_matrix *A;
   its_status s = new_matrix(&A);
   if (s != ITS_OK) return s;
@@ -750,6 +774,8 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
 its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
   if (!val_lo && A->nnz > 0) return fail(ITS_E_INVALID, "null values");
+  if (reinterpret_cast<uintptr_t>(val_lo) % 16)
+    return fail(ITS_E_INVALID, "low-precision values must be 16-byte aligned");
   if (dtype == ITS_F32) A->val32 = static_cast<const float *>(val_lo);
   else if (dtype == ITS_F16) A->val16 = static_cast<const __half *>(val_lo);
   else return fail(ITS_E_INVALID, "dtype must be ITS_F32 or ITS_F16");
@@ -837,7 +863,13 @@ its_status its_dot(int64_t n, const double *x, const double *y, double *result, 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(kBlock), 0, s, st, 1, R);
   const int G = grid_for(n);
   hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, s, int32_t(n), x, y, R);
-  hipLaunchKernelGGL((k_finish<1, FinDot>), dim3(finish_grid(G)), dim3(kBlock), 0, s, R, G, FinDot{st, 0});
+  const int nb = finish_grid(G);
+  if (nb == 1) {
+    hipLaunchKernelGGL((k_finish_final<1, FinDot>), dim3(1), dim3(kBlock), 0, s, R, G, 1, FinDot{st, 0});
+  } else {
+    hipLaunchKernelGGL(k_finish_group<1>, dim3(nb), dim3(kBlock), 0, s, R, G);
+    hipLaunchKernelGGL((k_finish_final<1, FinDot>), dim3(1), dim3(kBlock), 0, s, R, nb, 2, FinDot{st, 0});
+  }
   HIP_TRY(hipGetLastError());
   double v = 0.0;
   HIP_TRY(hipMemcpyAsync(&v, &st->dot[0], sizeof(double), hipMemcpyDeviceToHost, s));

@@ -11,12 +11,11 @@ namespace its {
 
 // ------------------------------------------------------------------ basics
 
-// Zero nstates consecutive States and the finishing kernel's counter.
+// Zero nstates consecutive States.
 __global__ void k_reset(State *st, int nstates, Reduce *R) {
   uint32_t *w = reinterpret_cast<uint32_t *>(st);
   const int words = int(sizeof(State) / 4) * nstates;
   for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
-  if (threadIdx.x == 0) R->count = 0u;
 }
 
 // ------------------------------------------------------ scalar updates
@@ -63,11 +62,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Op A, const double *__restrict_
   });
 }
 
-// r = b - A x (r may be null) and r.r (finished by FinDot).
+// r = b - A x (r may be null; entry i stored at r[i * rstride]) and r.r
+// (finished by FinDot).
 template <class Op>
 __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *r,
-                                                     Reduce *R) {
+                                                     int rstride, Reduce *R) {
   __shared__ typename Op::Smem sm;
   auto xj = [&](int32_t j) { return x[j]; };
   Dot2 a;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restr
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
       const double ri = ld_nt(b + i) - acc;
-      if (r) st_nt(r + i, ri);
+      if (r) st_nt(r + int64_t(i) * rstride, ri);
       a.add(ri, ri);
     }
   });
@@ -96,17 +96,22 @@ __global__ void __launch_bounds__(kBlock) k_fill(int32_t n, double *x, double v)
 //           q = A p, alpha = rho / (p.q)
 //   pass 2: p = r + beta p stored, x += alpha p, r -= alpha q, rho' = r.r,
 //           convergence test, beta = rho'/rho
-// At the first iteration p = r.
+// At the first iteration p = r.  r and p are stored interleaved as pairs
+// {r_i, p_i}, so pass 1 gathers both with one access per column.
 
 template <class Op, class T>
-__global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A, const T *__restrict__ r,
-                                                     const T *__restrict__ p, T *__restrict__ q,
-                                                     const State *st, Reduce *R) {
+__global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
+                                                     const typename Pair<T>::type *__restrict__ rp,
+                                                     T *__restrict__ q, const State *st,
+                                                     Reduce *R) {
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
   const T beta = T(st->beta);
-  auto pj = [&](int32_t j) -> T { return first ? r[j] : fmaT(beta, p[j], r[j]); };
+  auto pj = [&](int32_t j) -> T {
+    const typename Pair<T>::type v = rp[j];
+    return first ? v.x : fmaT(beta, v.y, v.x);
+  };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
     T acc = T(0);
@@ -135,22 +140,27 @@ struct FinCg1 {
 };
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x, T *__restrict__ r,
-                                                     T *__restrict__ p, const T *__restrict__ q,
-                                                     const State *st, Reduce *R) {
+__global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x,
+                                                     typename Pair<T>::type *__restrict__ rp,
+                                                     const T *__restrict__ q, const State *st,
+                                                     Reduce *R) {
+  using P2 = typename Pair<T>::type;
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
   const T beta = T(st->beta), alpha = T(st->alpha);
   Dot2 a;
   for_rows(n, [&](int32_t i) {
-    const T r0 = ld_nt(r + i);
-    const T pi = first ? r0 : fmaT(beta, ld_nt(p + i), r0);
+    const P2 v = ld_nt(rp + i);
+    const T r0 = v.x;
+    const T pi = first ? r0 : fmaT(beta, v.y, r0);
     const T xi = ld_nt(x + i);
     const T qi = ld_nt(q + i);
-    st_nt(p + i, pi);
     st_nt(x + i, fmaT(alpha, pi, xi));
     const T ri = fmaT(-alpha, qi, r0);
-    st_nt(r + i, ri);
+    P2 o;
+    o.x = ri;
+    o.y = pi;
+    st_nt(rp + i, o);
     a.add(double(ri), double(ri));
   });
   DD v[1] = {a.get()};
@@ -502,13 +512,14 @@ struct FinBicgC {
 // Outer step: rh = (float)(r/rn), d = 0, rh.rh; then (after the inner CG)
 // x += rn * d in double.
 
+// rh is the first member of the inner {r, p} pairs (stride 2).
 __global__ void __launch_bounds__(kBlock) k_ir_scale(int32_t n, const double *__restrict__ r,
                                                      float *__restrict__ rh, float *__restrict__ d,
                                                      Reduce *R, double rn) {
   Dot2 a;
   for_rows(n, [&](int32_t i) {
     const float v = float(r[i] / rn);
-    rh[i] = v;
+    rh[2 * int64_t(i)] = v;
     d[i] = 0.0f;
     a.add(double(v), double(v));
   });

@@ -23,8 +23,37 @@ __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ float widen(__half v) { return __half2float(v); }
 
+// Copies elements [c0, c1) of a 16-byte aligned array to LDS so that element
+// k lands at dst[k - ka], ka = c0 rounded down to a 16-byte unit (returned).
+// Whole 16-byte units inside [ka, c1 rounded down) go by LDS-DMA
+// (global_load_lds_dwordx4: lane l of a wave writes dst_wave + 16 l); the
+// remaining tail of fewer than one unit by plain loads.  Nothing outside
+// [ka, c1) is read.  The caller waits (s_waitcnt) and synchronises the block
+// before reading dst.
+typedef __attribute__((address_space(1))) void global_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <class T>
+__device__ __forceinline__ int32_t copy_to_lds(const T *__restrict__ src, int32_t c0, int32_t c1,
+                                               T *dst) {
+  constexpr int E = 16 / sizeof(T);
+  const int32_t ka = c0 & ~(E - 1), kb = c1 & ~(E - 1);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t units = (kb - ka) / E;
+  for (int32_t u0 = w * 64; u0 < units; u0 += kBlock) {
+    const int32_t u = u0 + lane;
+    if (u < units)
+      __builtin_amdgcn_global_load_lds((global_void *)(src + ka + u * E), (lds_void *)(dst + u0 * E),
+                                       16, 0, 0);
+  }
+  const int32_t k = max(kb, c0) + int32_t(threadIdx.x);
+  if (k < c1) dst[k - ka] = src[k];
+  return ka;
+}
+
 // CSR: int32 row pointers and columns, values of type V (double, float or
-// __half; half values are widened exactly to float).  T is the arithmetic
+// __half; half values are widened exactly to float).  col and val must be
+// 16-byte aligned (checked when the matrix is created).  T is the arithmetic
 // type of the chain (double for FP64, float for the mixed-precision inner
 // solve).
 template <class V, class T>
@@ -35,15 +64,15 @@ struct CsrOp {
   int32_t n;
 
   // A tile's entries are a contiguous slab of col/val.  It is copied to LDS
-  // in chunks of kCap entries with coalesced loads (the rows' own strided
-  // reads of col/val would touch every cache line once per entry), then each
-  // thread walks its row from LDS.  Rows longer than a chunk continue their
-  // chain across chunks, so any row length works.
+  // in chunks of kCap entries (the rows' own strided reads of col/val would
+  // touch every cache line once per entry), then each thread walks its row
+  // from LDS.  Rows longer than a chunk continue their chain across chunks,
+  // so any row length works.  The copy goes straight from memory to LDS
+  // (global_load_lds, 16 bytes per lane) without passing through registers.
   static constexpr int kCap = 2048;
-  static constexpr int kLoads = kCap / kBlock;
   struct Smem {
-    V val[kCap];
-    int32_t col[kCap];
+    V val[kCap + 16 / sizeof(V)];
+    int32_t col[kCap + 4];
     int32_t rp[kBlock + 1];
   };
 
@@ -62,24 +91,9 @@ struct CsrOp {
     }
     for (int32_t c0 = k0; c0 < k1; c0 += kCap) {
       const int32_t c1 = min(k1, c0 + kCap);
-      V vv[kLoads];
-      int32_t cc[kLoads];
-#pragma unroll
-      for (int u = 0; u < kLoads; ++u) {
-        const int32_t k = c0 + t + u * kBlock;
-        if (k < c1) {
-          vv[u] = ld_nt(val + k);
-          cc[u] = ld_nt(col + k);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kLoads; ++u) {
-        const int32_t k = c0 + t + u * kBlock;
-        if (k < c1) {
-          sm.val[k - c0] = vv[u];
-          sm.col[k - c0] = cc[u];
-        }
-      }
+      const int32_t va = copy_to_lds(val, c0, c1, sm.val);
+      const int32_t ca = copy_to_lds(col, c0, c1, sm.col);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       const int32_t kb = max(b, c0), ke = min(e, c1);
       for (int32_t k = kb; k < ke; k += kGather) {
@@ -88,8 +102,8 @@ struct CsrOp {
 #pragma unroll
         for (int u = 0; u < kGather; ++u) {
           if (k + u < ke) {
-            cj[u] = sm.col[k + u - c0];
-            aj[u] = T(widen(sm.val[k + u - c0]));
+            cj[u] = sm.col[k + u - ca];
+            aj[u] = T(widen(sm.val[k + u - va]));
             xj[u] = fetch(cj[u]);
           }
         }
