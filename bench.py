@@ -27,8 +27,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "CG iters/s + achieved HBM GB/s, 256^3 Poisson; mixed-prec vs FP64 at 1e-8"
-KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/kernels.hpp", "paper_2305_05988_amd/csrc/common.hpp",
-                  "paper_2305_05988_amd/csrc/ops.hpp"]
+# the sources that define the CSR SpMV pass of CG (its traffic counters are
+# tied to their hash)
+KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/common.hpp", "paper_2305_05988_amd/csrc/rowops.hpp",
+                  "paper_2305_05988_amd/csrc/csr.hpp", "paper_2305_05988_amd/csrc/kernels_cg.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_pass1_poisson256_traffic.txt")
 # Inside the timed region every PROFILE_EVERY-th launch of each kernel is
 # bracketed by HIP events: enough samples for the per-launch average, few

@@ -1,27 +1,10 @@
-// Matrix operators.  Every operator applies row i as a fused multiply-add
-// chain over the row's entries in ascending column order, starting from +0,
-// with the vector entry x_j supplied by a fetch functor f(j) -- so a kernel
-// can apply A to a vector it forms on the fly (p = r + beta p, s = r - alpha v)
-// without storing it first.  The SpMV of the paper (Sections 2.1-2.2) is
-// the chain with f(j) = x[j].
-//
-// Tiles: kernels walk the rows in tiles of kBlock rows, one row per thread,
-// through tile_entries(r0, r1, smem, fetch, consume): for the thread's row it
-// calls consume(j, a_ij, x_j) for every entry in stored order.  Entries are
-// handled in groups of kGather: all fetches of a group are issued before the
-// first consume, so a thread keeps up to kGather gathers in flight while the
-// chain itself stays strictly sequential.
+// CSR operator: LDS-DMA staged tiles of a CSR matrix (see rowops.hpp for the
+// row-walk contract).
 #pragma once
 
-#include "common.hpp"
+#include "rowops.hpp"
 
 namespace its {
-
-constexpr int kGather = 8;
-
-__device__ __forceinline__ double widen(double v) { return v; }
-__device__ __forceinline__ float widen(float v) { return v; }
-__device__ __forceinline__ float widen(__half v) { return __half2float(v); }
 
 // Copies elements [c0, c1) of a 16-byte aligned array to LDS so that element
 // k lands at dst[k - ka], ka = c0 rounded down to a 16-byte unit (returned).
@@ -31,6 +14,9 @@ __device__ __forceinline__ float widen(__half v) { return __half2float(v); }
 // [ka, c1) is read.  The caller waits (s_waitcnt) and synchronises the block
 // before reading dst.
 typedef __attribute__((address_space(1))) void global_void;
+// Cache-policy operand of the LDS-DMA load: the non-temporal bit (the "nt"
+// bit of the gfx94x/gfx950 cache-policy field), as for the streaming loads.
+constexpr int kCachePolicyNT = 2;
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <class T>
@@ -44,10 +30,10 @@ __device__ __forceinline__ int32_t copy_to_lds(const T *__restrict__ src, int32_
     const int32_t u = u0 + lane;
     if (u < units)
       __builtin_amdgcn_global_load_lds((global_void *)(src + ka + u * E), (lds_void *)(dst + u0 * E),
-                                       16, 0, 0);
+                                       16, 0, kCachePolicyNT);
   }
   const int32_t k = max(kb, c0) + int32_t(threadIdx.x);
-  if (k < c1) dst[k - ka] = src[k];
+  if (k < c1) dst[k - ka] = ld_nt(src + k);
   return ka;
 }
 
@@ -132,80 +118,6 @@ struct CsrOp {
         diag = a;
       else
         off = fmaT(a, xv, off);
-    }
-  }
-};
-
-// Matrix-free constant-coefficient stencil on nx*ny*nz, row = i + nx(j + ny k).
-// Neighbours outside the grid are skipped, exactly as the CSR rows of the
-// same operator omit them, so both give bit-identical chains.  NPTS = 7:
-// offsets (k-1, j-1, i-1, centre, i+1, j+1, k+1); NPTS = 27: dk outer, dj, di
-// inner.  Coefficients in that (ascending column) order.
-template <int NPTS, class T>
-struct StencilOp {
-  int32_t nx, ny, nz, n;
-  T c[NPTS];
-
-  struct Smem {};
-
-  __device__ __forceinline__ void coords(int32_t i, int32_t &ix, int32_t &iy, int32_t &iz) const {
-    const int32_t t = i / nx;
-    ix = i - t * nx;
-    iz = t / ny;
-    iy = t - iz * ny;
-  }
-
-  template <class Fetch, class Consume>
-  __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &, Fetch &&fetch,
-                                               Consume &&consume) const {
-    const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) row_entries(i, fetch, consume);
-  }
-
-  template <class Fetch, class Consume>
-  __device__ __forceinline__ void row_entries(int32_t i, Fetch &&fetch, Consume &&consume) const {
-    int32_t ix, iy, iz;
-    coords(i, ix, iy, iz);
-    row_entries_at(i, ix, iy, iz, fetch, consume);
-  }
-
-  template <class Fetch, class Consume>
-  __device__ __forceinline__ void row_entries_at(int32_t i, int32_t ix, int32_t iy, int32_t iz,
-                                                 Fetch &&fetch, Consume &&consume) const {
-    const int32_t nxy = nx * ny;
-    if constexpr (NPTS == 7) {
-      const bool has[7] = {iz > 0, iy > 0, ix > 0, true, ix < nx - 1, iy < ny - 1, iz < nz - 1};
-      const int32_t d[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
-      T xv[7];
-#pragma unroll
-      for (int o = 0; o < 7; ++o)
-        if (has[o]) xv[o] = fetch(i + d[o]);
-#pragma unroll
-      for (int o = 0; o < 7; ++o)
-        if (has[o]) consume(i + d[o], c[o], xv[o]);
-    } else {
-#pragma unroll
-      for (int dk = -1; dk <= 1; ++dk) {
-        // one plane (9 entries) of gathers in flight at a time
-        T xv[9];
-        bool in[9];
-#pragma unroll
-        for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-          for (int di = -1; di <= 1; ++di) {
-            const int u = (dj + 1) * 3 + (di + 1);
-            in[u] = (iz + dk >= 0) && (iz + dk < nz) && (iy + dj >= 0) && (iy + dj < ny) &&
-                    (ix + di >= 0) && (ix + di < nx);
-            if (in[u]) xv[u] = fetch(i + dk * nxy + dj * nx + di);
-          }
-#pragma unroll
-        for (int dj = -1; dj <= 1; ++dj)
-#pragma unroll
-          for (int di = -1; di <= 1; ++di) {
-            const int u = (dj + 1) * 3 + (di + 1);
-            if (in[u]) consume(i + dk * nxy + dj * nx + di, c[(dk + 1) * 9 + u], xv[u]);
-          }
-      }
     }
   }
 };

@@ -1,0 +1,108 @@
+// Conjugate gradient passes (FP64, and FP32 for the refinement's inner solve).
+#pragma once
+
+#include "common.hpp"
+#include "rowops.hpp"
+
+namespace its {
+
+// ---------------------------------------------------------------------- CG
+// Classical CG, two fused passes per iteration (T = double, or float for the
+// inner solve of the mixed-precision refinement):
+//   pass 1: p = r + beta p formed on the fly for every gathered column,
+//           q = A p, alpha = rho / (p.q)
+//   pass 2: p = r + beta p stored, x += alpha p, r -= alpha q, rho' = r.r,
+//           convergence test, beta = rho'/rho
+// At the first iteration p = r.  r and p are stored interleaved as pairs
+// {r_i, p_i}, so pass 1 gathers both with one access per column.
+
+template <class Op, class T>
+__global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
+                                                     const typename Pair<T>::type *__restrict__ rp,
+                                                     T *__restrict__ q, const State *st,
+                                                     Reduce *R) {
+  __shared__ typename Op::Smem sm;
+  if (st->flag != kRunning) return;
+  const bool first = st->k == 0;
+  const T beta = T(st->beta);
+  auto pj = [&](int32_t j) -> T {
+    const typename Pair<T>::type v = rp[j];
+    return first ? v.x : fmaT(beta, v.y, v.x);
+  };
+  Dot2 a;
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    T acc = T(0);
+    A.tile_entries(r0, r1, sm, pj, [&](int32_t, T av, T v) { acc = fmaT(av, v, acc); });
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    if (i < r1) {
+      st_nt(q + i, acc);
+      a.add(double(pj(i)), double(acc));
+    }
+  });
+  DD v[1] = {a.get()};
+  block_partial<1>(v, R);
+}
+
+// alpha = rho / (p.q); p.q = 0 or non-finite is a breakdown.
+struct FinCg1 {
+  State *st;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
+    const double pq = dd_round(v[0]);
+    if (pq == 0.0 || !finite(pq))
+      st->flag = kBreakdown;
+    else
+      st->alpha = st->rho / pq;
+  }
+};
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x,
+                                                     typename Pair<T>::type *__restrict__ rp,
+                                                     const T *__restrict__ q, const State *st,
+                                                     Reduce *R) {
+  using P2 = typename Pair<T>::type;
+  if (st->flag != kRunning) return;
+  const bool first = st->k == 0;
+  const T beta = T(st->beta), alpha = T(st->alpha);
+  Dot2 a;
+  for_rows(n, [&](int32_t i) {
+    const P2 v = ld_nt(rp + i);
+    const T r0 = v.x;
+    const T pi = first ? r0 : fmaT(beta, v.y, r0);
+    const T xi = ld_nt(x + i);
+    const T qi = ld_nt(q + i);
+    st_nt(x + i, fmaT(alpha, pi, xi));
+    const T ri = fmaT(-alpha, qi, r0);
+    P2 o;
+    o.x = ri;
+    o.y = pi;
+    st_nt(rp + i, o);
+    a.add(double(ri), double(ri));
+  });
+  DD v[1] = {a.get()};
+  block_partial<1>(v, R);
+}
+
+// rho' = r.r, one more iteration, beta = rho'/rho, convergence test.
+struct FinCg2 {
+  State *st;
+  double thr2;
+  int64_t max_iter;
+  __device__ bool active() const { return st->flag == kRunning; }
+  __device__ void operator()(DD (&v)[1]) const {
+    const double rho_new = dd_round(v[0]);
+    const int64_t k = st->k + 1;
+    st->k = k;
+    st->beta = rho_new / st->rho;
+    st->rho = rho_new;
+    if (rho_new <= thr2)
+      st->flag = kConverged;
+    else if (!finite(rho_new))
+      st->flag = kBreakdown;
+    else if (k >= max_iter)
+      st->flag = kMaxIter;
+  }
+};
+
+}  // namespace its

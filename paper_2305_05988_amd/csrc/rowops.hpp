@@ -1,0 +1,26 @@
+// Matrix operators.  Every operator applies row i as a fused multiply-add
+// chain over the row's entries in ascending column order, starting from +0,
+// with the vector entry x_j supplied by a fetch functor f(j) -- so a kernel
+// can apply A to a vector it forms on the fly (p = r + beta p, s = r - alpha v)
+// without storing it first.  The SpMV of the paper (Sections 2.1-2.2) is
+// the chain with f(j) = x[j].
+//
+// Tiles: kernels walk the rows in tiles of kBlock rows, one row per thread,
+// through tile_entries(r0, r1, smem, fetch, consume): for the thread's row it
+// calls consume(j, a_ij, x_j) for every entry in stored order.  Entries are
+// handled in groups of kGather: all fetches of a group are issued before the
+// first consume, so a thread keeps up to kGather gathers in flight while the
+// chain itself stays strictly sequential.
+#pragma once
+
+#include "common.hpp"
+
+namespace its {
+
+constexpr int kGather = 8;
+
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(__half v) { return __half2float(v); }
+
+}  // namespace its
