@@ -50,10 +50,12 @@ def load(path):
     L.orc_jacobi.argtypes = [I64, P, P, P, P, P, D, I64, P]
     L.orc_sgs.argtypes = [I64, P, P, P, P, I32, P, P, D, I64, P]
     L.orc_cg.argtypes = [I64, P, P, P, P, P, D, I64, P]
+    L.orc_cgnb.argtypes = [I64, P, P, P, P, P, D, I64, P]
     L.orc_bicgstab.argtypes = [I64, P, P, P, P, P, D, I64, D, I32, P]
     L.orc_ir_cg.argtypes = [I64, P, P, P, P, P, P, D, I64, D, I64, P]
     L.orc_lu_solve.argtypes = [I64, P, P]
-    for f in ("orc_jacobi", "orc_sgs", "orc_cg", "orc_bicgstab", "orc_ir_cg", "orc_lu_solve"):
+    for f in ("orc_jacobi", "orc_sgs", "orc_cg", "orc_cgnb", "orc_bicgstab", "orc_ir_cg",
+              "orc_lu_solve"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -152,6 +154,14 @@ def cg(A, b, x0=None, rtol=1e-8, max_iter=1000):
     rp, col, val, n, b, x = _prep(A, b, x0)
     r = _Result()
     lib().orc_cg(n, _p(rp), _p(col), _p(val), _p(b), _p(x), rtol, max_iter, C.byref(r))
+    return x, _res(r)
+
+
+def cgnb(A, b, x0=None, rtol=1e-8, max_iter=1000):
+    """The paper's nonblocking CG (Algorithm 1, sign of the x update fixed)."""
+    rp, col, val, n, b, x = _prep(A, b, x0)
+    r = _Result()
+    lib().orc_cgnb(n, _p(rp), _p(col), _p(val), _p(b), _p(x), rtol, max_iter, C.byref(r))
     return x, _res(r)
 
 

@@ -405,6 +405,99 @@ int orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
 }
 
 /* ------------------------------------------------------------------------ */
+/* CG-NB, the paper's nonblocking CG (Algorithm 1): the SpMV is applied to r  */
+/* and A p is carried by the recurrence A p_j = A r_j + beta_j A p_{j-1}, so   */
+/* the dot of r_j can overlap the SpMV (Section 2.1).                          */
+/*   init: r0 = b - A x0, p0 = r0, (A p)0 = A r0, alpha_n = r0.r0,            */
+/*         alpha_d = (A p)0.p0, alpha = alpha_n / alpha_d                      */
+/*   j >= 1: r_j = r_{j-1} - alpha_{j-1} (A p)_{j-1}; alpha_n,j = r_j.r_j;     */
+/*         beta = alpha_n,j / alpha_n,j-1; (A p)_j = A r_j + beta (A p)_{j-1}; */
+/*         p_j = r_j + beta p_{j-1}; alpha_d,j = (A p)_j.p_j;                  */
+/*         x_j = x_{j-1} + gamma (p_j - r_j),                                  */
+/*         gamma = alpha_n,j-1^2 / (alpha_d,j-1 alpha_n,j)                      */
+/* Readings:                                                                  */
+/*  - sign: Algorithm 1 subtracts in the x update and in the final update;     */
+/*    from p_j = r_j + beta_j p_{j-1} and x_j = x_{j-1} + alpha_{j-1} p_{j-1}  */
+/*    the update is an addition (gamma (p_j - r_j) = alpha_{j-1} p_{j-1}).     */
+/*  - the test is applied to r_j after x_j has been formed, and x_j (whose    */
+/*    residual r_j is) is returned: no extra final update.                    */
+/*  - the x update is the paper's three-term kernel z = a x + b y + c z with   */
+/*    a = gamma, b = -gamma, c = 1: x = fma(gamma, p, fma(-gamma, r, x)).      */
+/*  - alpha_d = 0 (or non-finite) is a breakdown with x unchanged.             */
+/* ------------------------------------------------------------------------ */
+int orc_cgnb(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+             const double *b, double *x, double rtol, int64_t max_iter, orc_result *res) {
+  double bb, thr2 = 0.0, an, ad, alpha;
+  int64_t i, k;
+  double *r, *p, *ap, *w;
+  if (solve_prologue(n, b, x, rtol, &bb, &thr2, res)) return res->status;
+  r = (double *)malloc(sizeof(double) * (size_t)n);
+  p = (double *)malloc(sizeof(double) * (size_t)n);
+  ap = (double *)malloc(sizeof(double) * (size_t)n);
+  w = (double *)malloc(sizeof(double) * (size_t)n);
+  residual(n, rp, col, val, b, x, r);
+  an = orc_dot(n, r, r);
+  k = 0;
+  if (an <= thr2) {
+    res->status = ORC_OK;
+  } else if (!isfinite(an)) {
+    res->status = ORC_BREAKDOWN;
+  } else if (max_iter <= 0) {
+    res->status = ORC_NOT_CONVERGED;
+  } else {
+    memcpy(p, r, sizeof(double) * (size_t)n);
+    orc_spmv(n, rp, col, val, r, ap);
+    ad = orc_dot(n, ap, p);
+    if (ad == 0.0 || !isfinite(ad)) {
+      res->status = ORC_BREAKDOWN;
+    } else {
+      alpha = an / ad;
+      for (k = 1;; k++) {
+        double an_new, beta, gamma, ad_new;
+        for (i = 0; i < n; i++) r[i] = fma(-alpha, ap[i], r[i]);
+        an_new = orc_dot(n, r, r);
+        beta = an_new / an;
+        gamma = (an * an) / (ad * an_new);
+        orc_spmv(n, rp, col, val, r, w);
+        for (i = 0; i < n; i++) {
+          ap[i] = fma(beta, ap[i], w[i]);
+          p[i] = fma(beta, p[i], r[i]);
+          x[i] = fma(gamma, p[i], fma(-gamma, r[i], x[i]));
+        }
+        ad_new = orc_dot(n, ap, p);
+        an = an_new;
+        if (an <= thr2) {
+          res->status = ORC_OK;
+          break;
+        }
+        if (!isfinite(an)) {
+          res->status = ORC_BREAKDOWN;
+          break;
+        }
+        if (k == max_iter) {
+          res->status = ORC_NOT_CONVERGED;
+          break;
+        }
+        if (ad_new == 0.0 || !isfinite(ad_new)) {
+          res->status = ORC_BREAKDOWN;
+          break;
+        }
+        ad = ad_new;
+        alpha = an / ad;
+      }
+    }
+  }
+  res->iters = k;
+  res->rel_res = sqrt(an) / sqrt(bb);
+  res->true_rel_res = true_rel_res(n, rp, col, val, b, x, bb);
+  free(r);
+  free(p);
+  free(ap);
+  free(w);
+  return res->status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* BiCGStab with the operation list of Algorithm 2 (BiCGStab-B1), which is   */
 /* arithmetically the classical method (Section 2.1), including its restart.  */
 /*   init: r = b - A x, p = r, beta = r.r, r' = r/sqrt(beta), alpha_n = r.r'  */

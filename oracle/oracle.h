@@ -56,6 +56,8 @@ int orc_sgs(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
             int64_t max_iter, orc_result *res);
 int orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
            const double *b, double *x, double rtol, int64_t max_iter, orc_result *res);
+int orc_cgnb(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+             const double *b, double *x, double rtol, int64_t max_iter, orc_result *res);
 int orc_bicgstab(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
                  const double *b, double *x, double rtol, int64_t max_iter,
                  double restart_tol, int32_t restart_mode, orc_result *res);

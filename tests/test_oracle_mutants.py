@@ -22,8 +22,14 @@ MUTANTS = [
      [lambda: S.test_cg_matches_dense_lu(S.inputs.poisson7_csr, (6, 5, 4))]),
     ("cg beta inverted", "beta = rho_new / rho;", "beta = rho / rho_new;",
      [lambda: S.test_cg_matches_dense_lu(S.inputs.poisson7_csr, (6, 5, 4))]),
-    ("cg direction update drops r", "p[i] = fma(beta, p[i], r[i]);", "p[i] = beta * p[i];",
+    ("cg direction update drops r", "for (i = 0; i < n; i++) p[i] = fma(beta, p[i], r[i]);",
+     "for (i = 0; i < n; i++) p[i] = beta * p[i];",
      [lambda: S.test_cg_finite_termination(3, 7)]),
+    ("cgnb update sign as printed", "x[i] = fma(gamma, p[i], fma(-gamma, r[i], x[i]));",
+     "x[i] = fma(-gamma, p[i], fma(gamma, r[i], x[i]));",
+     [lambda: S.test_cgnb_matches_dense_lu(S.inputs.poisson7_csr, (6, 5, 4))]),
+    ("cgnb recurrence drops beta", "ap[i] = fma(beta, ap[i], w[i]);", "ap[i] = w[i];",
+     [lambda: S.test_cgnb_finite_termination(3, 7)]),
     ("bicgstab omega term dropped", "x[i] = fma(omega, s[i], fma(alpha, p[i], x[i]));",
      "x[i] = fma(alpha, p[i], x[i]);",
      [lambda: S.test_bicgstab_matches_dense_lu_upwind((5, 5, 5))]),

@@ -172,6 +172,63 @@ def test_cg_fixed_k_iterate_is_deterministic():
     assert np.array_equal(x1, x2)
 
 
+# ------------------------------------------------------------------ CG-NB
+@pytest.mark.parametrize("N,distinct", [(2, 4), (3, 7)])
+def test_cgnb_finite_termination(N, distinct):
+    # arithmetically CG (Algorithm 1 only reorders it), so its residual
+    # vanishes within the number of distinct eigenvalues too
+    A = inputs.poisson7_csr(N)
+    xs, b = _system(A, seed=3)
+    x, r = oracle.cgnb(A, b, rtol=1e-13, max_iter=100)
+    assert r.status == oracle.OK and r.iters <= distinct
+    assert r.rel_res <= 1e-13
+
+
+def test_cgnb_x_update_cancels_when_beta_collapses():
+    # Algorithm 1 forms x_j from gamma (p_j - r_j) with gamma ~ 1/alpha_n,j;
+    # when the residual collapses in one step (finite termination), beta ~ 0,
+    # p_j - r_j cancels and the rounding error is amplified: the iterate loses
+    # accuracy although the recursive residual vanished.  Classical CG does not.
+    A = inputs.poisson7_csr(2)
+    xs, b = _system(A, seed=3)
+    x, r = oracle.cgnb(A, b, rtol=1e-13, max_iter=100)
+    xc, rc = oracle.cg(A, b, rtol=1e-13, max_iter=100)
+    assert r.true_rel_res > 1e-6 and rc.true_rel_res < 1e-14
+
+
+@pytest.mark.parametrize("gen,g", [(inputs.poisson7_csr, (6, 5, 4)),
+                                   (inputs.stencil27_csr, (5, 5, 5))])
+def test_cgnb_matches_dense_lu(gen, g):
+    A = gen(*g)
+    xs, b = _system(A, seed=11)
+    x, r = oracle.cgnb(A, b, rtol=1e-12, max_iter=1000)
+    assert r.status == oracle.OK
+    ref = oracle.lu_solve(oracle.csr_to_dense(A), b)
+    assert np.max(np.abs(x - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k", [1, 3, 10])
+def test_cgnb_iterates_track_classical_cg(k):
+    # same Krylov iterates in exact arithmetic; rounding differs slightly
+    A = inputs.poisson7_csr(9, 8, 7)
+    xs, b = _system(A, seed=5)
+    x1, r1 = oracle.cg(A, b, rtol=0.0, max_iter=k)
+    x2, r2 = oracle.cgnb(A, b, rtol=0.0, max_iter=k)
+    assert r1.iters == r2.iters == k
+    assert np.max(np.abs(x1 - x2)) <= 1e-12 * np.max(np.abs(x1))
+
+
+def test_cgnb_converges_like_cg_with_small_residual_gap():
+    N = 16
+    A = inputs.poisson7_csr(N)
+    xs, b = _system(A, seed=1)
+    xc, rc = oracle.cg(A, b, rtol=1e-8, max_iter=2000)
+    xn, rn = oracle.cgnb(A, b, rtol=1e-8, max_iter=2000)
+    assert rn.status == oracle.OK and abs(rn.iters - rc.iters) <= 1
+    assert rn.true_rel_res <= 1.1e-8
+    assert np.linalg.norm(xn - xc) / np.linalg.norm(xc) <= 1e-8
+
+
 # ------------------------------------------------------------- BiCGStab
 @pytest.mark.parametrize("g", [(5, 5, 5), (8, 3, 6)])
 def test_bicgstab_matches_dense_lu_upwind(g):
