@@ -237,6 +237,12 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
         mp[f"ir_{lowp}_rel_diff_vs_fp64_cg"] = (xl - x64).norm().item() / x64.norm().item()
     ex["mixed_precision_256"] = mp
     log(f"mixed precision: {json.dumps(mp)}")
+    # the paper's CG-NB (Algorithm 1) on the same CSR system
+    its.solve(A, b, method="cgnb", rtol=args.rtol, max_iter=20000)
+    t, (xn, info) = timed(lambda: its.solve(A, b, method="cgnb", rtol=args.rtol, max_iter=20000))
+    ex["cgnb_256_csr"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t,
+                          "achieved_gbs": info.iters / t * (12 * nnz + 4 * (n + 1) + 12 * V) / 1e9,
+                          "true_rel_res": info.true_rel_res, "vs_cg_time": t / t64}
     # matrix-free stencil CG on the same grid
     S = its.StencilMatrix(N, N, N, inputs.POISSON7)
     its.solve(S, b, method="cg", rtol=args.rtol, max_iter=20000)

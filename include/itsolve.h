@@ -45,7 +45,7 @@ typedef enum {
   ITS_E_UNSUPPORTED = -4 /* valid request this build does not support */
 } its_status;
 
-typedef enum { ITS_JACOBI = 0, ITS_SGS = 1, ITS_CG = 2, ITS_BICGSTAB = 3 } its_method;
+typedef enum { ITS_JACOBI = 0, ITS_SGS = 1, ITS_CG = 2, ITS_BICGSTAB = 3, ITS_CG_NB = 4 } its_method;
 typedef enum { ITS_F64 = 0, ITS_F32 = 1, ITS_F16 = 2 } its_dtype;
 typedef enum { ITS_RESTART_COSINE = 0, ITS_RESTART_PAPER = 1 } its_restart_mode;
 
@@ -82,7 +82,8 @@ typedef struct {
   /* profile != 0 only: summed duration and count of the timed launches per
      kernel class (6 = finishing reductions, 7 = setup and bookkeeping).
      CG: 0 = SpMV+dot pass, 1 = update+dot pass.  BiCGStab: 0 = A p pass,
-     1 = A s pass, 2 = update pass.  Jacobi: 0 = sweep.  SGS: 0 = colour
+     1 = A s pass, 2 = update pass.  CG-NB: 0 = SpMV pass X, 1 = update pass
+     Y.  Jacobi: 0 = sweep.  SGS: 0 = colour
      half-sweeps, 1 = residual.  IR: 0/1 = inner passes as CG, 2 = outer
      residual, 3 = outer scaling and update. */
   double kernel_ms[ITS_MAX_KERNEL_CLASSES];
@@ -168,7 +169,10 @@ its_status its_workspace_size(const its_matrix *A, const its_options *opts, size
      ITS_CG       classical CG (Hestenes-Stiefel), or mixed-precision IR;
      ITS_BICGSTAB BiCGStab with the arithmetic of Algorithm 2 and its
                   restart: COSINE restarts when |r.r'| < restart_tol ||r||,
-                  PAPER when sqrt(|r.r'|) < restart_tol.
+                  PAPER when sqrt(|r.r'|) < restart_tol;
+     ITS_CG_NB    the paper's nonblocking CG (Algorithm 1): SpMV on r, A p by
+                  recurrence, x updated through gamma (p_j - r_j) (added; the
+                  printed minus sign is a typo).
    Returns ITS_OK / ITS_NOT_CONVERGED / ITS_BREAKDOWN with res filled and x
    holding the returned iterate, or a negative error with x untouched.
    res: host, out. */

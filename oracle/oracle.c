@@ -424,6 +424,8 @@ int orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
 /*  - the x update is the paper's three-term kernel z = a x + b y + c z with   */
 /*    a = gamma, b = -gamma, c = 1: x = fma(gamma, p, fma(-gamma, r, x)).      */
 /*  - alpha_d = 0 (or non-finite) is a breakdown with x unchanged.             */
+/*  - if alpha_n,j = 0 exactly (exact convergence), gamma divides by zero;     */
+/*    the update takes its exact value alpha_{j-1} p_{j-1}.                    */
 /* ------------------------------------------------------------------------ */
 int orc_cgnb(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
              const double *b, double *x, double rtol, int64_t max_iter, orc_result *res) {
@@ -460,9 +462,13 @@ int orc_cgnb(int64_t n, const int64_t *rp, const int32_t *col, const double *val
         gamma = (an * an) / (ad * an_new);
         orc_spmv(n, rp, col, val, r, w);
         for (i = 0; i < n; i++) {
+          const double p_old = p[i];
           ap[i] = fma(beta, ap[i], w[i]);
           p[i] = fma(beta, p[i], r[i]);
-          x[i] = fma(gamma, p[i], fma(-gamma, r[i], x[i]));
+          if (an_new == 0.0) /* gamma = 1/0: take the exact limit alpha p_old */
+            x[i] = fma(alpha, p_old, x[i]);
+          else
+            x[i] = fma(gamma, p[i], fma(-gamma, r[i], x[i]));
         }
         ad_new = orc_dot(n, ap, p);
         an = an_new;

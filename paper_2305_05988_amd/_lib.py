@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, "libitsolve.so")
 
 ITS_OK, ITS_NOT_CONVERGED, ITS_BREAKDOWN = 0, 1, 2
 ITS_E_INVALID, ITS_E_HIP, ITS_E_WORKSPACE, ITS_E_UNSUPPORTED = -1, -2, -3, -4
-ITS_JACOBI, ITS_SGS, ITS_CG, ITS_BICGSTAB = 0, 1, 2, 3
+ITS_JACOBI, ITS_SGS, ITS_CG, ITS_BICGSTAB, ITS_CG_NB = 0, 1, 2, 3, 4
 ITS_F64, ITS_F32, ITS_F16 = 0, 1, 2
 ITS_RESTART_COSINE, ITS_RESTART_PAPER = 0, 1
 MAX_KERNEL_CLASSES = 8

@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 
 _METHODS = {"jacobi": L.ITS_JACOBI, "sgs": L.ITS_SGS, "gs": L.ITS_SGS, "cg": L.ITS_CG,
-            "bicgstab": L.ITS_BICGSTAB}
+            "bicgstab": L.ITS_BICGSTAB, "cgnb": L.ITS_CG_NB}
 _DTYPES = {"f64": L.ITS_F64, "f32": L.ITS_F32, "f16": L.ITS_F16}
 _RESTART = {"cosine": L.ITS_RESTART_COSINE, "paper": L.ITS_RESTART_PAPER}
 _STATUS = {L.ITS_OK: "ok", L.ITS_NOT_CONVERGED: "not_converged", L.ITS_BREAKDOWN: "breakdown"}

@@ -38,6 +38,7 @@ struct alignas(256) State {
   double alpha_n;     // BiCGStab r.r'
   double alpha_d;     // BiCGStab (A p).r'
   double ts, tt;      // BiCGStab (A s).s and (A s).(A s)
+  double gamma;       // CG-NB x-update coefficient
   double dot[4];      // scratch results (dot products, residual norms)
 };
 

@@ -156,6 +156,7 @@ struct Layout {
 //   CG       : {r, p} interleaved pairs (16), q (8)
 //   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
 //   BiCGStab : r, r', p0, p1, v0, v1, t (8 each)
+//   CG-NB    : {r, Ap} interleaved pairs (16), p (8), w = A r (8)
 Layout layout_for(int64_t n, int method, int inner_dtype) {
   Layout L;
   L.state = 0;
@@ -174,6 +175,7 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
       }
       break;
     case ITS_BICGSTAB: L.nreg = 7; for (int i = 0; i < 7; ++i) per[i] = 8; break;
+    case ITS_CG_NB: L.nreg = 3; per[0] = 16; per[1] = 8; per[2] = 8; break;
     default: break;
   }
   for (int i = 0; i < L.nreg; ++i) {
@@ -354,6 +356,54 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
         FINISH(run, 1, w.R, G, (FinCg1{w.st}));
         LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, rp, (const double *)q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCg2{w.st, thr2, o->max_iter}));
+        return ITS_OK;
+      });
+    });
+    if (s != ITS_OK) return s;
+  } else {
+    s = poll(run, w.st, h);
+    if (s != ITS_OK) return s;
+  }
+  res->status = flag_to_status(h->flag);
+  res->iters = h->k;
+  res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  return true_residual(run, A, w, b, x, h, bb, res);
+}
+
+// ---------------------------------------------------------------- CG-NB
+
+its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const double *b,
+                      double *x, const WS &w, its_result *res) {
+  State *h = A->host_state;
+  const int32_t n = int32_t(A->n);
+  const int G = grid_for(n);
+  double2_t *ra = w.reg<double2_t>(0);  // {r, Ap} pairs
+  double *p = w.v64(1), *wv = w.v64(2);
+  double bb, rr;
+  its_status s = prologue(run, A, w, b, x, reinterpret_cast<double *>(ra), 2, h, bb, rr);
+  if (s != ITS_OK) return s;
+  if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
+  if (bb == 0.0) {
+    LAUNCH(run, kClassOther, k_fill, G, n, x, 0.0);
+    HIP_TRY(hipStreamSynchronize(run.s));
+    res->status = ITS_OK;
+    return ITS_OK;
+  }
+  const double thr2 = threshold2(o->rtol, bb);
+  int32_t flag = kRunning;
+  if (rr <= thr2) flag = kConverged;
+  else if (!std::isfinite(rr)) flag = kBreakdown;
+  else if (o->max_iter <= 0) flag = kMaxIter;
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
+  if (flag == kRunning) {
+    s = with_op64(A, [&](auto op) -> its_status {
+      LAUNCH(run, kClassOther, k_cgnb_init<decltype(op)>, G, op, ra, p, w.R);
+      FINISH(run, 1, w.R, G, (FinCgnbInit{w.st}));
+      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
+        LAUNCH(run, 0, k_cgnb_x<decltype(op)>, G, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinCgnbX{w.st}));
+        LAUNCH(run, 1, k_cgnb_y, G, n, x, ra, p, (const double *)wv, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G, (FinCgnbY{w.st, thr2, o->max_iter}));
         return ITS_OK;
       });
     });
@@ -627,7 +677,7 @@ its_status check_diag(Run &run, its_matrix *A, const WS &w) {
 }
 
 bool options_ok(const its_options *o, std::string &why) {
-  if (o->method < ITS_JACOBI || o->method > ITS_BICGSTAB) { why = "unknown method"; return false; }
+  if (o->method < ITS_JACOBI || o->method > ITS_CG_NB) { why = "unknown method"; return false; }
   if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) { why = "rtol must be finite and >= 0"; return false; }
   if (o->max_iter < 0) { why = "max_iter must be >= 0"; return false; }
   if (!(o->restart_tol >= 0.0) || !std::isfinite(o->restart_tol)) { why = "restart_tol must be finite and >= 0"; return false; }
@@ -921,6 +971,7 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
       s = o->inner_dtype == ITS_F64 ? solve_cg(run, A, o, b, x, w, res) : solve_ir(run, A, o, b, x, w, res);
       break;
     case ITS_BICGSTAB: s = solve_bicgstab(run, A, o, b, x, w, res); break;
+    case ITS_CG_NB: s = solve_cgnb(run, A, o, b, x, w, res); break;
     case ITS_JACOBI: s = solve_jacobi(run, A, o, b, x, w, res); break;
     default: s = solve_sgs(run, A, o, b, x, w, res); break;
   }

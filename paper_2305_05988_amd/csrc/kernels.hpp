@@ -8,6 +8,7 @@
 #include "kernels_basic.hpp"
 #include "kernels_bicgstab.hpp"
 #include "kernels_cg.hpp"
+#include "kernels_cgnb.hpp"
 #include "kernels_ir.hpp"
 #include "kernels_relax.hpp"
 #include "kernels_util.hpp"

@@ -191,6 +191,33 @@ def test_cg_nonzero_initial_guess():
     assert info.iters == rr.iters and rel(host(x), ref) <= 1e-10
 
 
+# ------------------------------------------------------------------ CG-NB
+
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27"])
+@pytest.mark.parametrize("k", [1, 2, 7, 40])
+def test_cgnb_fixed_k_iterates(kind, k):
+    Acsr, A = _matrix(kind, (19, 13, 11))
+    xs, b = _system(Acsr)
+    ref, rr = oracle.cgnb(Acsr, b, rtol=0.0, max_iter=k)
+    x, info = its().solve(A, dev(b), method="cgnb", rtol=0.0, max_iter=k)
+    xg = host(x)
+    assert info.status == "not_converged" and info.iters == k == rr.iters
+    assert rel(xg, ref) <= 1e-10, f"max ulps {ulps(xg, ref)}"
+    assert ulps(xg, ref) == 0
+
+
+@pytest.mark.parametrize("kind", ["csr7", "sten7"])
+def test_cgnb_converged_32cube(kind):
+    Acsr, A = _matrix(kind, (32, 32, 32))
+    xs, b = _system(Acsr, seed=1)
+    ref, rr = oracle.cgnb(Acsr, b, rtol=1e-8, max_iter=5000)
+    x, info = its().solve(A, dev(b), method="cgnb", rtol=1e-8, max_iter=5000)
+    xg = host(x)
+    assert rr.status == oracle.OK and info.status == "ok"
+    assert abs(info.iters - rr.iters) <= 1 and rel(xg, ref) <= 1e-10
+    assert info.true_rel_res <= 1.01e-8
+
+
 # ------------------------------------------------------------------ Jacobi
 
 @pytest.mark.parametrize("kind", ["csr7", "sten7", "csrcd", "sten27"])
@@ -328,7 +355,7 @@ def test_ir_cg_matches_oracle(kind, lowp):
 
 # ------------------------------------------------------- edge cases / status
 
-@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab"])
+@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab", "cgnb"])
 def test_zero_rhs(method):
     A = its().StencilMatrix(5, 4, 3, inputs.POISSON7)
     x, info = its().solve(A, torch.zeros(60, dtype=torch.float64, device="cuda"),
@@ -336,7 +363,7 @@ def test_zero_rhs(method):
     assert info.status == "ok" and info.iters == 0 and not host(x).any()
 
 
-@pytest.mark.parametrize("method", ["jacobi", "cg", "bicgstab"])
+@pytest.mark.parametrize("method", ["jacobi", "cg", "bicgstab", "cgnb"])
 def test_nan_rhs_is_invalid(method):
     A = its().StencilMatrix(5, 4, 3, inputs.POISSON7)
     b = np.ones(60)
@@ -346,7 +373,7 @@ def test_nan_rhs_is_invalid(method):
     assert e.value.status == -1
 
 
-@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab"])
+@pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab", "cgnb"])
 def test_max_iter_zero(method):
     Acsr, A = _matrix("sten7", (6, 5, 4))
     xs, b = _system(Acsr)
@@ -356,7 +383,7 @@ def test_max_iter_zero(method):
 
 def test_single_unknown():
     A = its().CSRMatrix.from_numpy(np.array([0, 1]), np.array([0]), np.array([4.0]))
-    for method in ("jacobi", "cg", "bicgstab"):
+    for method in ("jacobi", "cg", "bicgstab", "cgnb"):
         x, info = its().solve(A, dev(np.array([3.0])), method=method, rtol=1e-14, max_iter=10)
         assert info.status == "ok" and host(x)[0] == 0.75
 

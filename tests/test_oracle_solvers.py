@@ -184,6 +184,13 @@ def test_cgnb_finite_termination(N, distinct):
     assert r.rel_res <= 1e-13
 
 
+def test_cgnb_exact_convergence_uses_the_limit_update():
+    # one unknown: r vanishes after one step, alpha_n = 0, gamma = 1/0
+    A = (np.array([0, 1], np.int64), np.array([0], np.int32), np.array([4.0]))
+    x, r = oracle.cgnb(A, np.array([3.0]), rtol=1e-14)
+    assert r.status == oracle.OK and r.iters == 1 and x[0] == 0.75
+
+
 def test_cgnb_x_update_cancels_when_beta_collapses():
     # Algorithm 1 forms x_j from gamma (p_j - r_j) with gamma ~ 1/alpha_n,j;
     # when the residual collapses in one step (finite termination), beta ~ 0,
