@@ -1,5 +1,8 @@
 """Benchmark: FP64 CG on the 256^3 Poisson 7-point CSR system to relative
-residual 1e-8 (x* ~ U[-1,1) seed 1, b = A x*, x0 = 0), one MI355X.
+residual 1e-8 (x* ~ U[-1,1) seed 1, b = A x*, x0 = 0), one MI355X.  The CSR
+matrix is handed to the library, which packs it into its device layout
+(sliced ELLPACK, its_csr_pack) during setup; --layout csr keeps the CSR
+arrays instead.
 
 A step is one complete solve.  The JSON line reports CG iterations per
 second over the timed steps, the roofline of the dominant kernel (the fused
@@ -9,6 +12,7 @@ mixed-precision refinement against FP64 CG at 1e-8 plus the other methods of
 the library on their workloads.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras] [--no-cpu]
+                    [--layout packed|csr]
 """
 from __future__ import annotations
 
@@ -30,7 +34,8 @@ METRIC = "CG iters/s + achieved HBM GB/s, 256^3 Poisson; mixed-prec vs FP64 at 1
 # the sources that define the CSR SpMV pass of CG (its traffic counters are
 # tied to their hash)
 KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/common.hpp", "paper_2305_05988_amd/csrc/rowops.hpp",
-                  "paper_2305_05988_amd/csrc/csr.hpp", "paper_2305_05988_amd/csrc/kernels_cg.hpp"]
+                  "paper_2305_05988_amd/csrc/csr.hpp", "paper_2305_05988_amd/csrc/sell.hpp",
+                  "paper_2305_05988_amd/csrc/kernels_cg.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_pass1_poisson256_traffic.txt")
 # Inside the timed region every PROFILE_EVERY-th launch of each kernel is
 # bracketed by HIP events: enough samples for the per-launch average, few
@@ -101,6 +106,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling: solve with rtol=0 for exactly this many iterations")
+    ap.add_argument("--layout", choices=("packed", "csr"), default="packed",
+                    help="device layout of the CSR matrix (packed: its_csr_pack)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -130,18 +137,26 @@ def main():
     t0 = time.perf_counter()
     rp, col, val = inputs.poisson7_csr(N)
     n, nnz = rp.size - 1, col.size
-    A = its.CSRMatrix.from_numpy(rp, col, val)
+    # low-precision copies of the values (mixed-precision refinement) are
+    # attached first, so packing covers them too
+    A = its.CSRMatrix.from_numpy(rp, col, val, lowp=("f32", "f16"),
+                                 pack=args.layout == "packed")
     del rp, col, val
     xs = torch.from_numpy(inputs.uniform_vector(n, 1)).cuda()
     b = its.spmv(A, xs)
     torch.cuda.synchronize()
-    log(f"setup {N}^3 CSR n={n} nnz={nnz} in {time.perf_counter() - t0:.1f}s")
+    slots = A.packed_slots
+    log(f"setup {N}^3 CSR n={n} nnz={nnz} layout {args.layout} (slots {slots}) in "
+        f"{time.perf_counter() - t0:.1f}s")
 
     M = csr_bytes(n, nnz)
     V = 8 * n
     bytes_iter = M + 10 * V
     bytes_pass1 = M + 3 * V  # read col, val, row_ptr, r and p (gathered); write q
     bytes_pass2 = 7 * V      # read x, r, p, q; write x, r, p
+    # bytes the packed layout itself moves in pass 1: padded slots of column
+    # and value, int64 slice offsets, no row pointers
+    moved_pass1 = 12 * slots + 8 * ((n + 63) // 64 + 1) + 3 * V if slots else bytes_pass1
 
     opts = dict(method="cg", rtol=args.rtol, max_iter=20000)
     if args.fixed_iters:
@@ -169,11 +184,12 @@ def main():
     avg2 = ms2 / max(l2, 1) * 1e-3
     sha = kernel_source_sha()
     traffic = measured_traffic(sha)
-    roof = {"bound": "hbm", "kernel": "k_cg_pass1 (CSR SpMV + p.q)",
+    kname = "packed CSR" if slots else "CSR"
+    roof = {"bound": "hbm", "kernel": f"k_cg_pass1 ({kname} SpMV + p.q)",
             "achieved": bytes_pass1 / avg1 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": bytes_pass1 / avg1 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_pass1, "avg_launch_us": avg1 * 1e6,
-            "launches": l1, "kernel_src_sha": sha,
+            "launches": l1, "kernel_src_sha": sha, "layout_bytes_per_launch": moved_pass1,
             "update_pass": {"kernel": "k_cg_pass2", "avg_launch_us": avg2 * 1e6,
                             "achieved": bytes_pass2 / avg2 / 1e9}}
     xerr = (x - xs).norm().item() / xs.norm().item()
@@ -184,7 +200,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"poisson7_{N}^3_csr_fp64_cg_rtol{args.rtol:g}", "n": n,
                    "nnz": nnz, "x_star": "U[-1,1) seed 1", "b": "A x*", "x0": 0,
-                   "iters_per_solve": info.iters},
+                   "iters_per_solve": info.iters,
+                   "device_layout": ("sliced ELLPACK, 64-row slices (its_csr_pack), "
+                                     f"{slots} slots" if slots else "CSR")},
         "achieved_gbs": its_per_s * bytes_iter / 1e9,
         "hbm_frac": its_per_s * bytes_iter / 1e9 / HBM_PEAK_GBS,
         "algorithmic_bytes_per_iter": bytes_iter,
@@ -220,8 +238,6 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     ex = {}
     V = 8 * n
     # mixed-precision refinement vs FP64 CG, same system, same tolerance
-    A.set_lowp(its.cast_values(A.val, "f32"))
-    A.set_lowp(its.cast_values(A.val, "f16"))
     t64, (x64, i64) = timed(lambda: its.solve(A, b, method="cg", rtol=args.rtol, max_iter=20000))
     mp = {"fp64_cg_s": t64, "fp64_iters": i64.iters}
     for lowp in ("f32", "f16"):
@@ -269,7 +285,7 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     # BiCGStab on 192^3 upwind convection-diffusion (Peclet 10)
     rp, col, val = inputs.convdiff7_csr(192)
     n2, nnz2 = rp.size - 1, col.size
-    C = its.CSRMatrix.from_numpy(rp, col, val)
+    C = its.CSRMatrix.from_numpy(rp, col, val, pack=args.layout == "packed")
     del rp, col, val
     x2 = torch.from_numpy(inputs.uniform_vector(n2, 1)).cuda()
     b2 = its.spmv(C, x2)
@@ -283,6 +299,17 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
                                        "solves_per_s": 1.0 / t,
                                        "achieved_gbs": info.iters / t * (2 * M2 + 17 * 8 * n2) / 1e9,
                                        "true_rel_res": info.true_rel_res}
+    del C, x2, b2, xb
+    if args.layout == "packed":
+        # the same CG solve with the matrix left in CSR (LDS-staged tiles)
+        rp, col, val = inputs.poisson7_csr(N)
+        U = its.CSRMatrix.from_numpy(rp, col, val, validate=False)
+        del rp, col, val
+        its.solve(U, b, method="cg", rtol=args.rtol, max_iter=20000)
+        t, (xu, info) = timed(lambda: its.solve(U, b, method="cg", rtol=args.rtol, max_iter=20000))
+        ex["cg_256_csr_unpacked"] = {"iters": info.iters, "iters_per_s": info.iters / t,
+                                     "identical_to_packed": bool(torch.equal(xu, x64))}
+        del U, xu
     log(f"extras: {json.dumps(ex)}")
     return ex
 

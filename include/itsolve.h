@@ -113,8 +113,32 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream);
 
 /* Attaches low-precision copies of the CSR values (same structure) for the
    mixed-precision CG: dtype ITS_F32 (float) or ITS_F16 (IEEE half).  Device
-   pointer, borrowed, 16-byte aligned.  One array per dtype may be attached. */
+   pointer, borrowed, 16-byte aligned.  One array per dtype may be attached.
+   ITS_E_INVALID once the matrix is packed (its_csr_pack). */
 its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
+
+/* Packs a CSR matrix into the library's device layout for the streaming
+   passes: sliced ELLPACK, one slice per 64 consecutive rows, slice width =
+   its longest row, entry j of the slice's 64 rows stored contiguously, and
+   column -1 in the slots past a row's end.  Every row keeps its stored
+   entry order, so results are bit-identical to the unpacked matrix; the
+   layout spares the row pointers and lets each wavefront read its rows'
+   entries with coalesced loads (the SpMV of Sections 2.1-2.2).
+   The packed copy (col, val and any low-precision values attached with
+   its_csr_set_lowp, which must come first) is allocated and owned by the
+   handle and freed by its_matrix_destroy or the next its_csr_pack; it is a
+   snapshot, so pack again after changing the values.  Solves and its_spmv
+   use it when present; Gauss-Seidel's colour sweeps keep the CSR arrays.
+   Padding slots are streamed like entries, so packing pays only for nearly
+   uniform row lengths: max_fill (>= 1) bounds the slots of the rows, the sum
+   over slices of (rows in the slice) x (slice width), by
+   max_fill * nnz + 64.  Synchronises `stream`.  Errors: ITS_E_INVALID for
+   row pointers out of order or range or a bad max_fill; ITS_E_UNSUPPORTED
+   (matrix left unpacked) when the bound is exceeded. */
+its_status its_csr_pack(its_matrix *A, double max_fill, void *stream);
+
+/* Slots of the packed layout (entries plus padding), 0 if not packed. */
+int64_t its_csr_packed_slots(const its_matrix *A);
 
 /* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 2.4:
    colours, red-black without rotation).  color: n uint8 (device) with values

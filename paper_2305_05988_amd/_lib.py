@@ -23,6 +23,7 @@ EXPORTS = (
     "its_csr_set_colors", "its_stencil_create", "its_matrix_destroy", "its_matrix_rows",
     "its_spmv", "its_dot_workspace_size", "its_dot", "its_workspace_size", "its_solve",
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
+    "its_csr_pack", "its_csr_packed_slots",
 )
 
 
@@ -60,6 +61,8 @@ def load(path: str = LIB_PATH):
         "its_csr_create": (st, [I64, I64, P, P, P, P]),
         "its_csr_validate": (st, [P, I32, P]),
         "its_csr_set_lowp": (st, [P, P, I32]),
+        "its_csr_pack": (st, [P, C.c_double, P]),
+        "its_csr_packed_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),
         "its_matrix_destroy": (st, [P]),

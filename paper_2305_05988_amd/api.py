@@ -74,10 +74,12 @@ class CSRMatrix(_Matrix):
         self.colors = None
 
     @classmethod
-    def from_numpy(cls, row_ptr, col, val, device="cuda", lowp=(), validate=True):
+    def from_numpy(cls, row_ptr, col, val, device="cuda", lowp=(), validate=True, pack=False,
+                   max_fill=1.2):
         """Uploads host CSR arrays (row_ptr narrowed to int32) and, for each
         dtype name in ``lowp`` ("f32", "f16"), a low-precision copy of the
-        values made by the library's cast kernel."""
+        values made by the library's cast kernel; ``pack`` then builds the
+        library's packed device layout (its_csr_pack with ``max_fill``)."""
         rp = np.asarray(row_ptr)
         if rp[-1] >= 2 ** 31:
             raise ValueError("nnz must be below 2^31")
@@ -87,7 +89,21 @@ class CSRMatrix(_Matrix):
         A = cls(t_rp, t_col, t_val, validate=validate)
         for d in lowp:
             A.set_lowp(cast_values(t_val, d))
+        if pack:
+            A.pack(max_fill)
         return A
+
+    def pack(self, max_fill=1.2):
+        """Builds the packed (sliced ELLPACK) device copy that solves and
+        spmv then use; returns the number of slots it holds.  Refused
+        (ItsError, ITS_E_UNSUPPORTED) when the rows would need more than
+        max_fill * nnz + 64 slots."""
+        L.check(L.lib().its_csr_pack(self._h, float(max_fill), _stream()), "its_csr_pack")
+        return self.packed_slots
+
+    @property
+    def packed_slots(self) -> int:
+        return int(L.lib().its_csr_packed_slots(self._h))
 
     def set_lowp(self, v):
         if v.dtype == torch.float32:

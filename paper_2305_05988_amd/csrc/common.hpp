@@ -220,13 +220,15 @@ __device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R) {
 }
 
 // The partials of a pass with G blocks are finished by one kernel when
-// G <= kGroup, else by two: k_finish_group (block b sums first-level
+// G <= kFinishOne, else by two: k_finish_group (block b sums first-level
 // partials kGroup*b .. kGroup*b+kGroup-1 into p2[b]) and k_finish_final over
-// the group sums.  Partials are combined in index order at both levels, so
+// the group sums.  The order of the additions is fixed at both levels, so
 // the total does not depend on scheduling, and no fence is needed: each
 // level reads what the previous kernel stored.  (An in-kernel "last block"
 // needs agent-scope fences, which on this GPU write back and invalidate L2
 // and cost more than the extra launch.)
+constexpr int kFinishOne = 16 * kBlock;
+
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_finish_group(Reduce *R, int G) {
   DD v[ND];
@@ -240,30 +242,41 @@ __global__ void __launch_bounds__(kBlock) k_finish_group(Reduce *R, int G) {
   }
 }
 
-// Single block: reduce `count` partials (from p1 if `level` is 1, else p2)
-// and apply Fin (the pass's scalar update) to the totals.
+// Single block: reduce `count` partials (from p1 if `level` is 1, else p2;
+// thread t adds partials t, t + kBlock, ... in that order) and apply Fin
+// (the pass's scalar update) to the totals.
 template <int ND, class Fin>
 __global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, int level, Fin fin) {
   if (!fin.active()) return;
-  DD v[ND];
-  const int j = int(threadIdx.x);
+  const DD *src[ND];
 #pragma unroll
-  for (int d = 0; d < ND; ++d)
-    v[d] = (j < count) ? (level == 1 ? R->p1[d][j] : R->p2[d][j]) : DD{0.0, 0.0};
+  for (int d = 0; d < ND; ++d) src[d] = level == 1 ? R->p1[d] : R->p2[d];
+  DD v[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) v[d] = DD{0.0, 0.0};
+  for (int j = int(threadIdx.x); j < count; j += kBlock) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) v[d] = dd_add(v[d], src[d][j]);
+  }
   block_reduce<ND>(v);
   if (threadIdx.x == 0) fin(v);
 }
 
-inline int finish_grid(int G) { return (G + kGroup - 1) / kGroup; }
+// Blocks of the first finishing level (0 when one kernel finishes).
+inline int finish_grid(int G) { return G <= kFinishOne ? 0 : (G + kGroup - 1) / kGroup; }
 
 // ---------------------------------------------------------------- launch size
 
-inline int grid_for(int64_t n) {
+inline int grid_for(int64_t n, int max_blocks = kMaxGrid) {
   int64_t tiles = (n + kBlock - 1) / kBlock;
   if (tiles < 1) tiles = 1;
-  int g = int(tiles < kMaxGrid ? tiles : kMaxGrid);
+  int g = int(tiles < max_blocks ? tiles : max_blocks);
   if (g >= 64) g -= g % kXcds;
   return g;
 }
+
+// Grid of a pass that applies operator Op.
+template <class Op>
+inline int op_grid(int64_t n) { return grid_for(n, Op::kMaxBlocks); }
 
 }  // namespace its

@@ -56,6 +56,7 @@ struct CsrOp {
   // so any row length works.  The copy goes straight from memory to LDS
   // (global_load_lds, 16 bytes per lane) without passing through registers.
   static constexpr int kCap = 2048;
+  static constexpr int kMaxBlocks = kMaxGrid;
   struct Smem {
     V val[kCap + 16 / sizeof(V)];
     int32_t col[kCap + 4];
@@ -84,15 +85,20 @@ struct CsrOp {
       const int32_t kb = max(b, c0), ke = min(e, c1);
       for (int32_t k = kb; k < ke; k += kGather) {
         int32_t cj[kGather];
-        T aj[kGather], xj[kGather];
+        T aj[kGather];
+        decltype(fetch(0)) xj[kGather];
 #pragma unroll
         for (int u = 0; u < kGather; ++u) {
+          cj[u] = r0;
+          aj[u] = T(0);
           if (k + u < ke) {
             cj[u] = sm.col[k + u - ca];
             aj[u] = T(widen(sm.val[k + u - va]));
-            xj[u] = fetch(cj[u]);
           }
         }
+        // slots past the row's end fetch row r0 (not consumed)
+#pragma unroll
+        for (int u = 0; u < kGather; ++u) xj[u] = fetch(cj[u]);
 #pragma unroll
         for (int u = 0; u < kGather; ++u)
           if (k + u < ke) consume(cj[u], aj[u], xj[u]);

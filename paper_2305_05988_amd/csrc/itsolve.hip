@@ -34,7 +34,29 @@ struct its_matrix {
   std::vector<int32_t> color_off;
   int diag_state = 0;  // CSR: 0 unchecked, 1 every row has a nonzero diagonal, -1 not
   State *host_state = nullptr;  // pinned snapshot buffer for polling
+  // Packed copy (its_csr_pack), owned: sliced ELLPACK of col/val and of the
+  // low-precision values that were set when it was packed.
+  int64_t *sp = nullptr;
+  int32_t *scol = nullptr;
+  double *sval = nullptr;
+  float *sval32 = nullptr;
+  __half *sval16 = nullptr;
+  int64_t sell_entries = 0;
 };
+
+static void free_packed(its_matrix *A) {
+  if (A->sp) (void)hipFree(A->sp);
+  if (A->scol) (void)hipFree(A->scol);
+  if (A->sval) (void)hipFree(A->sval);
+  if (A->sval32) (void)hipFree(A->sval32);
+  if (A->sval16) (void)hipFree(A->sval16);
+  A->sp = nullptr;
+  A->scol = nullptr;
+  A->sval = nullptr;
+  A->sval32 = nullptr;
+  A->sval16 = nullptr;
+  A->sell_entries = 0;
+}
 
 // ------------------------------------------------------------------ errors
 
@@ -120,7 +142,7 @@ struct Run {
   template <int ND, class Fin>
   hipError_t finish(Reduce *R, int G, Fin fin) {
     const int nb = finish_grid(G);
-    if (nb == 1) return launch(kClassFinish, k_finish_final<ND, Fin>, 1, R, G, 1, fin);
+    if (nb == 0) return launch(kClassFinish, k_finish_final<ND, Fin>, 1, R, G, 1, fin);
     hipError_t e = launch(kClassFinish, k_finish_group<ND>, nb, R, G);
     if (e != hipSuccess) return e;
     return launch(kClassFinish, k_finish_final<ND, Fin>, 1, R, nb, 2, fin);
@@ -207,7 +229,9 @@ WS carve(void *ws, const Layout &L, int64_t) {
 template <class F>
 its_status with_op64(const its_matrix *A, F &&f) {
   switch (A->kind) {
-    case kCsr: return f(CsrOp<double, double>{A->rp, A->col, A->val, int32_t(A->n)});
+    case kCsr:
+      if (A->sp) return f(SellOp<double, double>{A->sp, A->scol, A->sval, int32_t(A->n)});
+      return f(CsrOp<double, double>{A->rp, A->col, A->val, int32_t(A->n)});
     case kSten7: {
       StencilOp<7, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 7; ++o) op.c[o] = A->coef[o];
@@ -225,7 +249,11 @@ template <class F>
 its_status with_op32(const its_matrix *A, int dtype, F &&f) {
   switch (A->kind) {
     case kCsr:
-      if (dtype == ITS_F32) return f(CsrOp<float, float>{A->rp, A->col, A->val32, int32_t(A->n)});
+      if (dtype == ITS_F32) {
+        if (A->sp) return f(SellOp<float, float>{A->sp, A->scol, A->sval32, int32_t(A->n)});
+        return f(CsrOp<float, float>{A->rp, A->col, A->val32, int32_t(A->n)});
+      }
+      if (A->sp) return f(SellOp<__half, float>{A->sp, A->scol, A->sval16, int32_t(A->n)});
       return f(CsrOp<__half, float>{A->rp, A->col, A->val16, int32_t(A->n)});
     case kSten7: {
       StencilOp<7, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
@@ -292,8 +320,9 @@ its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b,
   LAUNCH(run, kClassOther, k_dot, G, n, b, b, w.R);
   FINISH(run, 1, w.R, G, (FinDot{w.st, 0}));
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, r, rstride, w.R);
-    FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
+    const int GA = op_grid<decltype(op)>(n);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, GA, op, b, x, r, rstride, w.R);
+    FINISH(run, 1, w.R, GA, (FinDot{w.st, 1}));
     return ITS_OK;
   });
   if (s != ITS_OK) return s;
@@ -311,10 +340,10 @@ double threshold2(double rtol, double bb) {
 
 its_status true_residual(Run &run, const its_matrix *A, const WS &w, const double *b,
                          const double *x, State *host, double bb, its_result *res) {
-  const int G = grid_for(A->n);
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    LAUNCH(run, kClassOther, k_residual<decltype(op)>, G, op, b, x, (double *)nullptr, 1, w.R);
-    FINISH(run, 1, w.R, G, (FinDot{w.st2, 2}));
+    const int GA = op_grid<decltype(op)>(A->n);
+    LAUNCH(run, kClassOther, k_residual<decltype(op)>, GA, op, b, x, (double *)nullptr, 1, w.R);
+    FINISH(run, 1, w.R, GA, (FinDot{w.st2, 2}));
     return ITS_OK;
   });
   if (s != ITS_OK) return s;
@@ -351,9 +380,10 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
+      const int GA = op_grid<decltype(op)>(n);
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
-        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), G, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinCg1{w.st}));
+        LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), GA, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
         LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, rp, (const double *)q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCg2{w.st, thr2, o->max_iter}));
         return ITS_OK;
@@ -397,11 +427,12 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
-      LAUNCH(run, kClassOther, k_cgnb_init<decltype(op)>, G, op, ra, p, w.R);
-      FINISH(run, 1, w.R, G, (FinCgnbInit{w.st}));
+      const int GA = op_grid<decltype(op)>(n);
+      LAUNCH(run, kClassOther, k_cgnb_init<decltype(op)>, GA, op, ra, p, w.R);
+      FINISH(run, 1, w.R, GA, (FinCgnbInit{w.st}));
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
-        LAUNCH(run, 0, k_cgnb_x<decltype(op)>, G, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinCgnbX{w.st}));
+        LAUNCH(run, 0, k_cgnb_x<decltype(op)>, GA, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, GA, (FinCgnbX{w.st}));
         LAUNCH(run, 1, k_cgnb_y, G, n, x, ra, p, (const double *)wv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCgnbY{w.st, thr2, o->max_iter}));
         return ITS_OK;
@@ -447,8 +478,9 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   for (;; ++outer) {
     if (outer > 0) {  // r = b - A x of the refined iterate
       s = with_op64(A, [&](auto op) -> its_status {
-        LAUNCH(run, 2, k_residual<decltype(op)>, G, op, b, (const double *)x, r, 1, w.R);
-        FINISH(run, 1, w.R, G, (FinDot{w.st, 1}));
+        const int GA = op_grid<decltype(op)>(n);
+        LAUNCH(run, 2, k_residual<decltype(op)>, GA, op, b, (const double *)x, r, 1, w.R);
+        FINISH(run, 1, w.R, GA, (FinDot{w.st, 1}));
         return ITS_OK;
       });
       if (s != ITS_OK) return s;
@@ -470,9 +502,10 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     if (!(rho_i <= ithr2)) {
       LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
       s = with_op32(A, dt, [&](auto op) -> its_status {
+        const int GA = op_grid<decltype(op)>(n);
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
-          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), G, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
-          FINISH(run, 1, w.R, G, (FinCg1{w.st2}));
+          LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
+          FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
           LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, G, (FinCg2{w.st2, ithr2, budget}));
           return ITS_OK;
@@ -524,12 +557,13 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
     const double rt2 = o->restart_tol * o->restart_tol;
     const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
     s = with_op64(A, [&](auto op) -> its_status {
+      const int GA = op_grid<decltype(op)>(n);
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         const int a = int(j & 1), c = a ^ 1;
-        LAUNCH(run, 0, k_bicg_a<decltype(op)>, G, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinBicgA{w.st}));
-        LAUNCH(run, 1, k_bicg_b<decltype(op)>, G, op, (const double *)r, (const double *)V[c], t, (const State *)w.st, w.R);
-        FINISH(run, 2, w.R, G, (FinBicgB{w.st}));
+        LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
+        LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double *)r, (const double *)V[c], t, (const State *)w.st, w.R);
+        FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
         LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, G, (FinBicgC{w.st, thr2, o->max_iter, rt2, paper}));
         return ITS_OK;
@@ -571,10 +605,11 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
   LAUNCH(run, kClassOther, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
   // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
   s = with_op64(A, [&](auto op) -> its_status {
+    const int GA = op_grid<decltype(op)>(n);
     return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
-      LAUNCH(run, 0, k_jacobi<decltype(op)>, G, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
-      FINISH(run, 1, w.R, G, (FinJacobi{w.st, thr2, o->max_iter}));
+      LAUNCH(run, 0, k_jacobi<decltype(op)>, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
+      FINISH(run, 1, w.R, GA, (FinJacobi{w.st, thr2, o->max_iter}));
       return ITS_OK;
     });
   });
@@ -635,6 +670,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   };
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
+      const int GA = op_grid<decltype(op)>(n);
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         for (int c = (j == 0 ? 0 : 1); c < nc; ++c) {
           its_status e = sweep(c);
@@ -644,8 +680,8 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
           its_status e = sweep(c);
           if (e != ITS_OK) return e;
         }
-        LAUNCH(run, 1, k_gs_check<decltype(op)>, G, op, b, (const double *)x, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinGs{w.st, thr2, o->max_iter}));
+        LAUNCH(run, 1, k_gs_check<decltype(op)>, GA, op, b, (const double *)x, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, GA, (FinGs{w.st, thr2, o->max_iter}));
         return ITS_OK;
       });
     });
@@ -792,6 +828,7 @@ its_status its_matrix_destroy(its_matrix *A) {
   if (!A) return ITS_OK;
   if (A->color_rows) (void)hipFree(A->color_rows);
   if (A->host_state) (void)hipHostFree(A->host_state);
+  free_packed(A);
   delete A;
   return ITS_OK;
 }
@@ -823,6 +860,7 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
 
 its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (A->sp) return fail(ITS_E_INVALID, "set low-precision values before its_csr_pack");
   if (!val_lo && A->nnz > 0) return fail(ITS_E_INVALID, "null values");
   if (reinterpret_cast<uintptr_t>(val_lo) % 16)
     return fail(ITS_E_INVALID, "low-precision values must be 16-byte aligned");
@@ -831,6 +869,90 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype) {
   else return fail(ITS_E_INVALID, "dtype must be ITS_F32 or ITS_F16");
   return ITS_OK;
 }
+
+namespace {
+struct DevTmp {  // device allocation freed on scope exit
+  void *p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (!(max_fill >= 1.0) || !std::isfinite(max_fill))
+    return fail(ITS_E_INVALID, "max_fill must be finite and >= 1");
+  free_packed(A);
+  const int64_t n = A->n, ns = (n + kSlice - 1) / kSlice;
+  if (n == 0) return ITS_OK;
+  hipStream_t s = S(stream);
+  DevTmp width, bad;
+  HIP_TRY(hipMalloc(&width.p, size_t(ns) * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&bad.p, sizeof(uint32_t)));
+  HIP_TRY(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
+  const int gw = int(std::min<int64_t>((ns + kBlock - 1) / kBlock, 65536));
+  hipLaunchKernelGGL(k_sell_width, dim3(gw), dim3(kBlock), 0, s, int32_t(n), int32_t(A->nnz), A->rp,
+                     static_cast<int32_t *>(width.p), static_cast<uint32_t *>(bad.p));
+  HIP_TRY(hipGetLastError());
+  std::vector<int32_t> hw(static_cast<size_t>(ns));
+  uint32_t hbad = 0;
+  HIP_TRY(hipMemcpyAsync(hw.data(), width.p, size_t(ns) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&hbad, bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hbad) return fail(ITS_E_INVALID, std::to_string(hbad) + " rows with invalid row pointers");
+  std::vector<int64_t> hsp(static_cast<size_t>(ns) + 1, 0);
+  for (int64_t q = 0; q < ns; ++q) hsp[size_t(q) + 1] = hsp[size_t(q)] + int64_t(kSlice) * hw[size_t(q)];
+  const int64_t total = hsp[size_t(ns)];
+  // slots of the real rows (the rows past n in the last slice do not count)
+  int64_t row_slots = 0;
+  for (int64_t q = 0; q < ns; ++q)
+    row_slots += std::min<int64_t>(kSlice, n - q * kSlice) * hw[size_t(q)];
+  if (double(row_slots) > max_fill * double(A->nnz) + kSlice)
+    return fail(ITS_E_UNSUPPORTED, "row lengths vary too much: the packed rows would hold " +
+                                       std::to_string(row_slots) + " slots for " +
+                                       std::to_string(A->nnz) + " entries");
+  its_matrix P;  // new arrays; moved into A once complete
+  hipError_t e = hipMalloc(&P.sp, size_t(ns + 1) * sizeof(int64_t));
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.scol, size_t(total) * sizeof(int32_t));
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.sval, size_t(total) * sizeof(double));
+  if (e == hipSuccess && total > 0 && A->val32) e = hipMalloc(&P.sval32, size_t(total) * sizeof(float));
+  if (e == hipSuccess && total > 0 && A->val16) e = hipMalloc(&P.sval16, size_t(total) * sizeof(__half));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P.sp, hsp.data(), size_t(ns + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && total > 0) {
+    const int gs = int(std::min<int64_t>((ns * kSlice + kBlock - 1) / kBlock, 65536));
+    const int32_t ni = int32_t(n);
+    hipLaunchKernelGGL(k_sell_scatter<double>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
+                       A->val, (const int64_t *)P.sp, P.scol, P.sval);
+    if (A->val32)
+      hipLaunchKernelGGL(k_sell_scatter<float>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
+                         A->val32, (const int64_t *)P.sp, (int32_t *)nullptr, P.sval32);
+    if (A->val16)
+      hipLaunchKernelGGL(k_sell_scatter<__half>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
+                         A->val16, (const int64_t *)P.sp, (int32_t *)nullptr, P.sval16);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_packed(&P);
+    return fail(ITS_E_HIP, std::string("packing: ") + hipGetErrorString(e));
+  }
+  A->sp = P.sp;
+  A->scol = P.scol;
+  A->sval = P.sval;
+  A->sval32 = P.sval32;
+  A->sval16 = P.sval16;
+  A->sell_entries = total;
+  P.sp = nullptr;
+  P.scol = nullptr;
+  P.sval = nullptr;
+  P.sval32 = nullptr;
+  P.sval16 = nullptr;
+  return ITS_OK;
+}
+
+int64_t its_csr_packed_slots(const its_matrix *A) { return A && A->sp ? A->sell_entries : 0; }
 
 its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolors, void *stream) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
@@ -883,10 +1005,9 @@ its_status its_spmv(const its_matrix *A, const double *x, double *y, void *strea
   if (A->n == 0) return ITS_OK;
   if (!x || !y) return fail(ITS_E_INVALID, "null vector");
   if (x == y) return fail(ITS_E_INVALID, "x and y alias");
-  const int64_t tiles = (A->n + kBlock - 1) / kBlock;
-  const int grid = int(std::min<int64_t>(tiles, int64_t(1) << 30));
   hipStream_t s = S(stream);
   its_status st = with_op64(A, [&](auto op) -> its_status {
+    const int grid = op_grid<decltype(op)>(A->n);
     hipLaunchKernelGGL(k_spmv<decltype(op)>, dim3(grid), dim3(kBlock), 0, s, op, x, y);
     return ITS_OK;
   });
@@ -914,7 +1035,7 @@ its_status its_dot(int64_t n, const double *x, const double *y, double *result, 
   const int G = grid_for(n);
   hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, s, int32_t(n), x, y, R);
   const int nb = finish_grid(G);
-  if (nb == 1) {
+  if (nb == 0) {
     hipLaunchKernelGGL((k_finish_final<1, FinDot>), dim3(1), dim3(kBlock), 0, s, R, G, 1, FinDot{st, 0});
   } else {
     hipLaunchKernelGGL(k_finish_group<1>, dim3(nb), dim3(kBlock), 0, s, R, G);

@@ -12,4 +12,5 @@
 #include "kernels_ir.hpp"
 #include "kernels_relax.hpp"
 #include "kernels_util.hpp"
+#include "sell.hpp"
 #include "stencil.hpp"

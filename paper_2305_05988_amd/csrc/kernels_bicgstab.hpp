@@ -46,13 +46,20 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
   const bool restart = st->restart;
   const double bet = st->beta, om = st->omega;
   const double rn = restart ? __builtin_sqrt(st->rho) : 1.0;
-  auto pj = [&](int32_t j) -> double {
-    return plain ? r[j] : fma(bet, fma(-om, vo[j], po[j]), r[j]);
+  // p_j from the loaded {r_j, p_j, v_j} (only r_j when p = r)
+  struct RPV {
+    double r, p, v;
   };
+  auto load = [&](int32_t j) -> RPV {
+    if (plain) return RPV{r[j], 0.0, 0.0};  // block-uniform
+    return RPV{r[j], po[j], vo[j]};
+  };
+  auto pv = [&](const RPV &e) -> double { return plain ? e.r : fma(bet, fma(-om, e.v, e.p), e.r); };
+  auto pj = [&](int32_t j) -> double { return pv(load(j)); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, pj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    A.tile_entries(r0, r1, sm, load, [&](int32_t, double av, const RPV &e) { acc = fma(av, pv(e), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
       st_nt(pn + i, pj(i));
@@ -95,11 +102,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restric
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const double alpha = st->alpha;
-  auto sj = [&](int32_t j) -> double { return fma(-alpha, v[j], r[j]); };
+  auto load = [&](int32_t j) -> double2_t {
+    double2_t e;
+    e.x = r[j];
+    e.y = v[j];
+    return e;
+  };
+  auto sv = [&](const double2_t &e) -> double { return fma(-alpha, e.y, e.x); };
+  auto sj = [&](int32_t j) -> double { return sv(load(j)); };
   Dot2 a0, a1;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, sj, [&](int32_t, double av, double x) { acc = fma(av, x, acc); });
+    A.tile_entries(r0, r1, sm, load, [&](int32_t, double av, const double2_t &e) { acc = fma(av, sv(e), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
       st_nt(t + i, acc);

@@ -23,20 +23,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
                                                      Reduce *R) {
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
+  using P2 = typename Pair<T>::type;
   const bool first = st->k == 0;
   const T beta = T(st->beta);
-  auto pj = [&](int32_t j) -> T {
-    const typename Pair<T>::type v = rp[j];
-    return first ? v.x : fmaT(beta, v.y, v.x);
-  };
+  auto load = [&](int32_t j) -> P2 { return rp[j]; };
+  auto pv = [&](const P2 &v) -> T { return first ? v.x : fmaT(beta, v.y, v.x); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
     T acc = T(0);
-    A.tile_entries(r0, r1, sm, pj, [&](int32_t, T av, T v) { acc = fmaT(av, v, acc); });
+    A.tile_entries(r0, r1, sm, load, [&](int32_t, T av, const P2 &v) { acc = fmaT(av, pv(v), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
       st_nt(q + i, acc);
-      a.add(double(pj(i)), double(acc));
+      a.add(double(pv(rp[i])), double(acc));
     }
   });
   DD v[1] = {a.get()};

@@ -65,18 +65,17 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_x(Op A, const double2_t *__rest
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const double alpha = st->alpha;
-  auto rj = [&](int32_t j) -> double {
-    const double2_t v = ra[j];
-    return fma(-alpha, v.y, v.x);
-  };
+  auto load = [&](int32_t j) -> double2_t { return ra[j]; };
+  auto rv = [&](const double2_t &v) -> double { return fma(-alpha, v.y, v.x); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, rj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    A.tile_entries(r0, r1, sm, load,
+                   [&](int32_t, double av, const double2_t &v) { acc = fma(av, rv(v), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
     if (i < r1) {
       st_nt(w + i, acc);
-      const double ri = rj(i);
+      const double ri = rv(ra[i]);
       a.add(ri, ri);
     }
   });

@@ -15,6 +15,7 @@ struct StencilOp {
   int32_t nx, ny, nz, n;
   T c[NPTS];
 
+  static constexpr int kMaxBlocks = kMaxGrid;
   struct Smem {};
 
   __device__ __forceinline__ void coords(int32_t i, int32_t &ix, int32_t &iy, int32_t &iz) const {
@@ -45,10 +46,10 @@ struct StencilOp {
     if constexpr (NPTS == 7) {
       const bool has[7] = {iz > 0, iy > 0, ix > 0, true, ix < nx - 1, iy < ny - 1, iz < nz - 1};
       const int32_t d[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
-      T xv[7];
+      // neighbours outside the grid fetch the row itself (not consumed)
+      decltype(fetch(0)) xv[7];
 #pragma unroll
-      for (int o = 0; o < 7; ++o)
-        if (has[o]) xv[o] = fetch(i + d[o]);
+      for (int o = 0; o < 7; ++o) xv[o] = fetch(has[o] ? i + d[o] : i);
 #pragma unroll
       for (int o = 0; o < 7; ++o)
         if (has[o]) consume(i + d[o], c[o], xv[o]);
@@ -56,7 +57,7 @@ struct StencilOp {
 #pragma unroll
       for (int dk = -1; dk <= 1; ++dk) {
         // one plane (9 entries) of gathers in flight at a time
-        T xv[9];
+        decltype(fetch(0)) xv[9];
         bool in[9];
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
@@ -65,7 +66,7 @@ struct StencilOp {
             const int u = (dj + 1) * 3 + (di + 1);
             in[u] = (iz + dk >= 0) && (iz + dk < nz) && (iy + dj >= 0) && (iy + dj < ny) &&
                     (ix + di >= 0) && (ix + di < nx);
-            if (in[u]) xv[u] = fetch(i + dk * nxy + dj * nx + di);
+            xv[u] = fetch(in[u] ? i + dk * nxy + dj * nx + di : i);
           }
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)

@@ -74,3 +74,5 @@ def test_host_side_argument_errors(lib):
     assert lib.its_stream_copy(P0, P0, -1, P0) == L.ITS_E_INVALID
     assert lib.its_matrix_destroy(P0) == L.ITS_OK
     assert lib.its_matrix_rows(P0) == -1
+    assert lib.its_csr_pack(P0, 1.2, P0) == L.ITS_E_INVALID
+    assert lib.its_csr_packed_slots(P0) == 0

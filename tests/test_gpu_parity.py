@@ -90,6 +90,8 @@ def test_spmv_bit_exact_csr_and_stencil(g, kind):
     ref = oracle.spmv(Acsr, x)
     A = its().CSRMatrix.from_numpy(*Acsr)
     assert np.array_equal(host(its().spmv(A, dev(x))), ref)
+    A.pack(max_fill=2.0)
+    assert np.array_equal(host(its().spmv(A, dev(x))), ref)
     S = its().StencilMatrix(*g, coef)
     assert np.array_equal(host(its().spmv(S, dev(x))), ref)
 
@@ -102,6 +104,62 @@ def test_spmv_empty_and_ragged_rows():
     x = inputs.uniform_vector(5, 4)
     A = its().CSRMatrix.from_numpy(rp, col, val)
     assert np.array_equal(host(its().spmv(A, dev(x))), oracle.spmv((rp, col, val), x))
+
+
+def _ragged_csr(n, seed, max_len=13):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, max_len + 1, n)
+    lens[::17] = 0
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([np.sort(rng.choice(n, size=k, replace=False)) for k in lens]
+                         ).astype(np.int32) if rp[-1] else np.zeros(0, np.int32)
+    val = rng.uniform(-2.0, 2.0, rp[-1])
+    return rp, col, val
+
+
+@pytest.mark.parametrize("n,max_len", [(1, 3), (63, 9), (64, 4), (200, 13), (1000, 5), (4099, 30)])
+def test_packed_layout_ragged_rows(n, max_len):
+    # empty rows, rows longer than a gather group, a partial last slice
+    Acsr = _ragged_csr(n, n + max_len, max_len)
+    rp = Acsr[0]
+    x = inputs.uniform_vector(n, 9)
+    ref = oracle.spmv(Acsr, x)
+    A = its().CSRMatrix.from_numpy(*Acsr)
+    slots = A.pack(max_fill=4.0)
+    lens = np.diff(rp)
+    widths = [lens[s:s + 64].max() for s in range(0, n, 64)]
+    assert slots == 64 * int(np.sum(widths))
+    assert np.array_equal(host(its().spmv(A, dev(x))), ref)
+
+
+def test_packed_layout_all_rows_empty():
+    A = its().CSRMatrix.from_numpy(np.zeros(101, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert A.pack() == 0
+    assert not host(its().spmv(A, dev(inputs.uniform_vector(100, 2)))).any()
+
+
+def test_pack_refuses_excess_padding():
+    # one dense row in the first slice: 64 * 640 slots for 1279 entries
+    n = 640
+    rp = np.concatenate([[0, n], n + np.arange(1, n)]).astype(np.int64)
+    col = np.concatenate([np.arange(n), np.arange(1, n)]).astype(np.int32)
+    val = inputs.uniform_vector(col.size, 3)
+    A = its().CSRMatrix.from_numpy(rp, col, val)
+    with pytest.raises(its().ItsError) as e:
+        A.pack(max_fill=16.0)
+    assert e.value.status == -4 and A.packed_slots == 0
+    with pytest.raises(its().ItsError) as e:
+        A.pack(max_fill=0.5)
+    assert e.value.status == -1
+    x = inputs.uniform_vector(n, 4)
+    assert np.array_equal(host(its().spmv(A, dev(x))), oracle.spmv((rp, col, val), x))
+
+
+def test_lowp_values_must_precede_packing():
+    Acsr = inputs.poisson7_csr(4, 4, 4)
+    A = its().CSRMatrix.from_numpy(*Acsr, pack=True, max_fill=2.0)
+    with pytest.raises(its().ItsError):
+        A.set_lowp(its().cast_values(A.val, "f32"))
 
 
 def test_cast_values_round_to_nearest():
@@ -128,6 +186,10 @@ def _system(Acsr, seed=1):
 
 
 def _matrix(kind, g):
+    if kind.endswith("p"):  # the same CSR matrix in the packed device layout
+        Acsr, A = _matrix(kind[:-1], g)
+        assert A.pack(max_fill=2.0) >= Acsr[1].size
+        return Acsr, A
     if kind == "csr7":
         Acsr = inputs.poisson7_csr(*g)
         return Acsr, its().CSRMatrix.from_numpy(*Acsr, lowp=("f32", "f16"))
@@ -146,7 +208,7 @@ def _matrix(kind, g):
     raise KeyError(kind)
 
 
-@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "csr7p", "csr27p"])
 @pytest.mark.parametrize("k", [1, 2, 7, 40])
 def test_cg_fixed_k_iterates(kind, k):
     Acsr, A = _matrix(kind, (19, 13, 11))
@@ -159,7 +221,7 @@ def test_cg_fixed_k_iterates(kind, k):
     assert ulps(xg, ref) == 0
 
 
-@pytest.mark.parametrize("kind", ["csr7", "sten7"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr7p"])
 def test_cg_converged_32cube(kind):
     Acsr, A = _matrix(kind, (32, 32, 32))
     xs, b = _system(Acsr, seed=1)
@@ -193,7 +255,7 @@ def test_cg_nonzero_initial_guess():
 
 # ------------------------------------------------------------------ CG-NB
 
-@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "csr7p"])
 @pytest.mark.parametrize("k", [1, 2, 7, 40])
 def test_cgnb_fixed_k_iterates(kind, k):
     Acsr, A = _matrix(kind, (19, 13, 11))
@@ -220,7 +282,7 @@ def test_cgnb_converged_32cube(kind):
 
 # ------------------------------------------------------------------ Jacobi
 
-@pytest.mark.parametrize("kind", ["csr7", "sten7", "csrcd", "sten27"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csrcd", "sten27", "csrcdp", "csr27p"])
 @pytest.mark.parametrize("k", [0, 1, 2, 25])
 def test_jacobi_fixed_k_bit_exact(kind, k):
     Acsr, A = _matrix(kind, (17, 9, 6))
@@ -255,7 +317,7 @@ def test_jacobi_converges_upwind():
 # ------------------------------------------------------------ Gauss-Seidel
 
 @pytest.mark.parametrize("k", [1, 2, 9])
-@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "sten27"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "sten27", "csr7p"])
 def test_sgs_fixed_k_bit_exact(kind, k):
     g = (11, 7, 6)
     Acsr, A = _matrix(kind, g)
@@ -294,7 +356,7 @@ def test_sgs_rejects_bad_colouring():
 
 # --------------------------------------------------------------- BiCGStab
 
-@pytest.mark.parametrize("kind", ["csrcd", "stencd", "csr7"])
+@pytest.mark.parametrize("kind", ["csrcd", "stencd", "csr7", "csrcdp"])
 @pytest.mark.parametrize("k", [1, 3, 12])
 def test_bicgstab_fixed_k(kind, k):
     Acsr, A = _matrix(kind, (18, 11, 9))
@@ -307,7 +369,7 @@ def test_bicgstab_fixed_k(kind, k):
     assert ulps(xg, ref) == 0
 
 
-@pytest.mark.parametrize("kind", ["csrcd", "stencd"])
+@pytest.mark.parametrize("kind", ["csrcd", "stencd", "csrcdp"])
 def test_bicgstab_converged(kind):
     Acsr, A = _matrix(kind, (40, 36, 30))
     xs, b = _system(Acsr, seed=1)
@@ -332,7 +394,7 @@ def test_bicgstab_restart_paths(mode, tol):
 
 # ---------------------------------------------------- mixed precision (IR)
 
-@pytest.mark.parametrize("kind", ["csr27", "sten27", "csr7"])
+@pytest.mark.parametrize("kind", ["csr27", "sten27", "csr7", "csr7p", "csr27p"])
 @pytest.mark.parametrize("lowp", ["f32", "f16"])
 def test_ir_cg_matches_oracle(kind, lowp):
     g = (24, 20, 18)
@@ -381,11 +443,12 @@ def test_max_iter_zero(method):
     assert info.status == "not_converged" and info.iters == 0 and not host(x).any()
 
 
-def test_single_unknown():
-    A = its().CSRMatrix.from_numpy(np.array([0, 1]), np.array([0]), np.array([4.0]))
+@pytest.mark.parametrize("pack", [False, True])
+def test_single_unknown(pack):
+    A = its().CSRMatrix.from_numpy(np.array([0, 1]), np.array([0]), np.array([4.0]), pack=pack)
     for method in ("jacobi", "cg", "bicgstab", "cgnb"):
         x, info = its().solve(A, dev(np.array([3.0])), method=method, rtol=1e-14, max_iter=10)
-        assert info.status == "ok" and host(x)[0] == 0.75
+        assert info.status == "ok" and host(x)[0] == 0.75, method
 
 
 def test_cg_breakdown_on_indefinite():
@@ -430,3 +493,27 @@ def test_workspace_too_small():
         api.L.check(api.L.lib().its_solve(A.handle, C.byref(o), api._ptr(b), api._ptr(x),
                                           api._ptr(ws), 1024, api._stream(), C.byref(r)), "solve")
     assert e.value.status == -3
+
+
+# ------------------------------------------------------------- full size
+
+def test_full_size_poisson256_packed_cg():
+    """The timed workload's matrix and launch configuration (256^3 Poisson,
+    packed CSR, FP64 CG): SpMV and two CG iterations compared with the
+    oracle over every row."""
+    g = (256, 256, 256)
+    print("full size: building 256^3 Poisson CSR", flush=True)
+    Acsr = inputs.poisson7_csr(*g)
+    n = Acsr[0].size - 1
+    A = its().CSRMatrix.from_numpy(*Acsr, validate=False, pack=True)
+    xs = inputs.uniform_vector(n, 1)
+    b = oracle.spmv(Acsr, xs)
+    bg = its().spmv(A, dev(xs))
+    assert np.array_equal(host(bg), b)
+    print("full size: SpMV bit-exact; oracle CG, 2 iterations", flush=True)
+    ref, rr = oracle.cg(Acsr, b, rtol=0.0, max_iter=2)
+    x, info = its().solve(A, bg, method="cg", rtol=0.0, max_iter=2)
+    xg = host(x)
+    assert info.iters == rr.iters == 2
+    assert ulps(xg, ref) == 0
+    assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
