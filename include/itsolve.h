@@ -119,11 +119,13 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
 
 /* Packs a CSR matrix into the library's device layout for the streaming
    passes: sliced ELLPACK, one slice per 64 consecutive rows, slice width =
-   its longest row, entry j of the slice's 64 rows stored contiguously, and
-   column -1 in the slots past a row's end.  Every row keeps its stored
-   entry order, so results are bit-identical to the unpacked matrix; the
-   layout spares the row pointers and lets each wavefront read its rows'
-   entries with coalesced loads (the SpMV of Sections 2.1-2.2).
+   its longest row, column -1 in the slots past a row's end; within a slice
+   each row's entries are kept in consecutive pairs (entries 2c and 2c+1 of
+   the 64 rows form one contiguous run of 64 pairs; an odd width ends with
+   single entries).  Every row keeps its stored entry order, so results are
+   bit-identical to the unpacked matrix; the layout spares the row pointers
+   and lets each wavefront read two entries of its 64 rows with one
+   coalesced access (the SpMV of Sections 2.1-2.2).
    The packed copy (col, val and any low-precision values attached with
    its_csr_set_lowp, which must come first) is allocated and owned by the
    handle and freed by its_matrix_destroy or the next its_csr_pack; it is a

@@ -58,11 +58,20 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
   auto pj = [&](int32_t j) -> double { return pv(load(j)); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    double acc = 0.0;
-    A.tile_entries(r0, r1, sm, load, [&](int32_t, double av, const RPV &e) { acc = fma(av, pv(e), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
+    double acc = 0.0, pi = 0.0;
+    bool have = false;  // p_i taken from the row's diagonal entry
+    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const RPV &e) {
+      const double p = pv(e);
+      acc = fma(av, p, acc);
+      if (j == i) {
+        pi = p;
+        have = true;
+      }
+    });
     if (i < r1) {
-      st_nt(pn + i, pj(i));
+      if (!have) pi = pj(i);
+      st_nt(pn + i, pi);
       st_nt(vn + i, acc);
       double rsi;
       if (restart) {
@@ -112,12 +121,21 @@ __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restric
   auto sj = [&](int32_t j) -> double { return sv(load(j)); };
   Dot2 a0, a1;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    double acc = 0.0;
-    A.tile_entries(r0, r1, sm, load, [&](int32_t, double av, const double2_t &e) { acc = fma(av, sv(e), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
+    double acc = 0.0, si = 0.0;
+    bool have = false;  // s_i taken from the row's diagonal entry
+    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const double2_t &e) {
+      const double sv_j = sv(e);
+      acc = fma(av, sv_j, acc);
+      if (j == i) {
+        si = sv_j;
+        have = true;
+      }
+    });
     if (i < r1) {
+      if (!have) si = sj(i);
       st_nt(t + i, acc);
-      a0.add(acc, sj(i));
+      a0.add(acc, si);
       a1.add(acc, acc);
     }
   });

@@ -30,12 +30,21 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
   auto pv = [&](const P2 &v) -> T { return first ? v.x : fmaT(beta, v.y, v.x); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    T acc = T(0);
-    A.tile_entries(r0, r1, sm, load, [&](int32_t, T av, const P2 &v) { acc = fmaT(av, pv(v), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
+    T acc = T(0), pi = T(0);
+    bool have = false;  // p_i taken from the row's diagonal entry
+    A.tile_entries(r0, r1, sm, load, [&](int32_t j, T av, const P2 &v) {
+      const T pj = pv(v);
+      acc = fmaT(av, pj, acc);
+      if (j == i) {
+        pi = pj;
+        have = true;
+      }
+    });
     if (i < r1) {
       st_nt(q + i, acc);
-      a.add(double(pv(rp[i])), double(acc));
+      if (!have) pi = pv(rp[i]);
+      a.add(double(pi), double(acc));
     }
   });
   DD v[1] = {a.get()};

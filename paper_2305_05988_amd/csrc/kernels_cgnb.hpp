@@ -69,13 +69,20 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_x(Op A, const double2_t *__rest
   auto rv = [&](const double2_t &v) -> double { return fma(-alpha, v.y, v.x); };
   Dot2 a;
   for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    double acc = 0.0;
-    A.tile_entries(r0, r1, sm, load,
-                   [&](int32_t, double av, const double2_t &v) { acc = fma(av, rv(v), acc); });
     const int32_t i = r0 + int32_t(threadIdx.x);
+    double acc = 0.0, ri = 0.0;
+    bool have = false;  // r_i taken from the row's diagonal entry
+    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const double2_t &v) {
+      const double rj = rv(v);
+      acc = fma(av, rj, acc);
+      if (j == i) {
+        ri = rj;
+        have = true;
+      }
+    });
     if (i < r1) {
       st_nt(w + i, acc);
-      const double ri = rv(ra[i]);
+      if (!have) ri = rv(ra[i]);
       a.add(ri, ri);
     }
   });

@@ -1,5 +1,5 @@
-// Packed CSR: sliced ELLPACK with one 64-row slice per wavefront (see
-// rowops.hpp for the row-walk contract).
+// Packed CSR: sliced ELLPACK with one 64-row slice per wavefront, entries
+// of a lane stored in pairs (see rowops.hpp for the row-walk contract).
 #pragma once
 
 #include "rowops.hpp"
@@ -8,31 +8,86 @@ namespace its {
 
 constexpr int kSlice = 64;  // rows per slice: one wave64
 
-// Slice s holds rows 64 s .. 64 s + 63.  Its width w_s is the longest row in
-// the slice; entry j (j < w_s) of the slice's lane l (row 64 s + l) sits at
-// sp[s] + 64 j + l, so the wave reads entry j of its 64 rows with one
-// coalesced access and needs neither row pointers nor LDS staging.  A row
-// keeps its entries in stored order; slots past its end hold column -1
-// (value 0) and are skipped, so the chain is the CSR chain bit for bit.
-// sp has ns + 1 entries (ns = ceil(n / 64)), sp[s + 1] - sp[s] = 64 w_s.
-template <class V, class T, int NG = 4>
+// Slice s holds rows 64 s .. 64 s + 63 and has width w_s, the longest row in
+// the slice; it occupies slots [sp[s], sp[s] + 64 w_s).  The slice's entries
+// are cut into chunks of two consecutive entries per row (the last chunk of
+// an odd width holds one): chunk c (entries 2c, 2c + 1) occupies slots
+// sp[s] + 128 c + [0, 64 m) with m = min(2, w_s - 2c) entries per lane, lane l
+// (row 64 s + l) at sp[s] + 128 c + m l.  A wave thus reads two entries of
+// all its 64 rows with one coalesced 8-byte (columns) or 16-byte (FP64
+// values) access per lane, and needs neither row pointers nor LDS staging.
+// A row keeps its entries in stored order; slots past its end hold column
+// -1 (value 0) and are skipped, so the chain is the CSR chain bit for bit.
+// sp has ns + 1 entries (ns = ceil(n / 64)).
+__host__ __device__ __forceinline__ int64_t sell_slot(int64_t base, int32_t w, int32_t j,
+                                                      int32_t lane) {
+  const int32_t c = j >> 1;
+  const int32_t m = min(2, w - 2 * c);
+  return base + 128 * int64_t(c) + int64_t(m) * lane + (j - 2 * c);
+}
+
+// Two consecutive values as one load.
+typedef int32_t int2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void ld_pair(const int32_t *p, int32_t &a, int32_t &b) {
+  const int2_t v = ld_nt(reinterpret_cast<const int2_t *>(p));
+  a = v.x;
+  b = v.y;
+}
+__device__ __forceinline__ void ld_pair(const double *p, double &a, double &b) {
+  const double2_t v = ld_nt(reinterpret_cast<const double2_t *>(p));
+  a = v.x;
+  b = v.y;
+}
+__device__ __forceinline__ void ld_pair(const float *p, float &a, float &b) {
+  const float2_t v = ld_nt(reinterpret_cast<const float2_t *>(p));
+  a = v.x;
+  b = v.y;
+}
+__device__ __forceinline__ void ld_pair(const __half *p, __half &a, __half &b) {
+  const uint32_t v = ld_nt(reinterpret_cast<const uint32_t *>(p));
+  a = __builtin_bit_cast(__half, static_cast<unsigned short>(v & 0xffffu));
+  b = __builtin_bit_cast(__half, static_cast<unsigned short>(v >> 16));
+}
+
+template <class V, class T>
 struct SellOp {
   const int64_t *__restrict__ sp;
   const int32_t *__restrict__ col;
   const V *__restrict__ val;
   int32_t n;
 
-  // Entries per group whose gathers are in flight together (4 keeps the
-  // passes at full occupancy, 8 waves per SIMD).
-  static constexpr int kChunk = NG;
-  // Grid of the packed passes: the resident capacity, 8 blocks of 4 waves
-  // on each of the 256 CUs, so that all blocks run at once and the tiles
-  // dealt round-robin within an XCD advance as one front (a plane of a 3-D
-  // grid is gathered again one step later, from L2).  With more blocks the
-  // later ones revisit neighbours long after they left L2.
-  static constexpr int kMaxBlocks = 2048;
+  static constexpr int kMaxBlocks = kMaxGrid;
 
   struct Smem {};
+
+  // Entries g .. g + W - 1 of the lane's row in a slice of width w (g even):
+  // all column and value loads, then all gathers, then the chain.  W is a
+  // compile-time constant, so the loads and gathers are straight-line code
+  // and stay in flight together.
+  template <int W, class Fetch, class Consume>
+  __device__ __forceinline__ void group(int64_t base, int32_t w, int32_t g, int lane,
+                                        int32_t standin, Fetch &&fetch, Consume &&consume) const {
+    int32_t cj[W];
+    V vj[W];
+#pragma unroll
+    for (int c = 0; 2 * c < W; ++c) {
+      const int64_t at = sell_slot(base, w, g + 2 * c, lane);
+      if (2 * c + 1 < W) {
+        ld_pair(col + at, cj[2 * c], cj[2 * c + 1]);
+        ld_pair(val + at, vj[2 * c], vj[2 * c + 1]);
+      } else {
+        cj[2 * c] = ld_nt(col + at);
+        vj[2 * c] = ld_nt(val + at);
+      }
+    }
+    // padding slots fetch a stand-in row (not consumed)
+    decltype(fetch(0)) xj[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) xj[u] = fetch(cj[u] >= 0 ? cj[u] : standin);
+#pragma unroll
+    for (int u = 0; u < W; ++u)
+      if (cj[u] >= 0) consume(cj[u], T(widen(vj[u])), xj[u]);
+  }
 
   template <class Fetch, class Consume>
   __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &, Fetch &&fetch,
@@ -42,29 +97,30 @@ struct SellOp {
     const int32_t s = __builtin_amdgcn_readfirstlane((r0 >> 6) + (int32_t(threadIdx.x) >> 6));
     if (s * kSlice >= r1) return;
     const int lane = threadIdx.x & 63;
-    const int64_t b = sp[s];
-    const int32_t w = int32_t((sp[s + 1] - b) >> 6);
-    const int32_t *c = col + b + lane;
-    const V *v = val + b + lane;
-    for (int32_t j0 = 0; j0 < w; j0 += kChunk) {
-      int32_t cj[kChunk];
-      T aj[kChunk];
-      decltype(fetch(0)) xj[kChunk];
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        cj[u] = -1;
-        aj[u] = T(0);
-        if (j0 + u < w) {  // wave-uniform
-          cj[u] = ld_nt(c + int64_t(j0 + u) * kSlice);
-          aj[u] = T(widen(ld_nt(v + int64_t(j0 + u) * kSlice)));
-        }
-      }
-      // padding slots fetch the slice's first row (not consumed)
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) xj[u] = fetch(cj[u] >= 0 ? cj[u] : s * kSlice);
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u)
-        if (cj[u] >= 0) consume(cj[u], aj[u], xj[u]);
+    const int64_t base = sp[s];
+    const int32_t w = int32_t((sp[s + 1] - base) >> 6);
+    const int32_t standin = s * kSlice;
+    // widths up to 7 (7-point stencils and the like) in one group; wider
+    // slices in groups of 4, which keeps the registers of the widest group
+    // within reach of 6 waves per SIMD
+    switch (w) {  // wave-uniform
+      case 0: return;
+      case 1: group<1>(base, w, 0, lane, standin, fetch, consume); return;
+      case 2: group<2>(base, w, 0, lane, standin, fetch, consume); return;
+      case 3: group<3>(base, w, 0, lane, standin, fetch, consume); return;
+      case 4: group<4>(base, w, 0, lane, standin, fetch, consume); return;
+      case 5: group<5>(base, w, 0, lane, standin, fetch, consume); return;
+      case 6: group<6>(base, w, 0, lane, standin, fetch, consume); return;
+      case 7: group<7>(base, w, 0, lane, standin, fetch, consume); return;
+      default: break;
+    }
+    int32_t g = 0;
+    for (; g + 4 <= w; g += 4) group<4>(base, w, g, lane, standin, fetch, consume);
+    switch (w - g) {
+      case 1: group<1>(base, w, g, lane, standin, fetch, consume); break;
+      case 2: group<2>(base, w, g, lane, standin, fetch, consume); break;
+      case 3: group<3>(base, w, g, lane, standin, fetch, consume); break;
+      default: break;
     }
   }
 };
@@ -106,7 +162,8 @@ __global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t n, const int32_
   const int64_t rows = (int64_t(n) + kSlice - 1) / kSlice * kSlice;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < rows;
        i += int64_t(gridDim.x) * kBlock) {
-    const int64_t s = i / kSlice, l = i % kSlice;
+    const int64_t s = i / kSlice;
+    const int32_t l = int32_t(i % kSlice);
     const int64_t base = sp[s];
     const int32_t w = int32_t((sp[s + 1] - base) / kSlice);
     int32_t b = 0, len = 0;
@@ -116,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t n, const int32_
       if (len < 0) len = 0;
     }
     for (int32_t j = 0; j < w; ++j) {
-      const int64_t at = base + int64_t(j) * kSlice + l;
+      const int64_t at = sell_slot(base, w, j, l);
       if (col_out) col_out[at] = j < len ? col[b + j] : -1;
       val_out[at] = j < len ? val[b + j] : V(0.0f);
     }
