@@ -275,8 +275,5 @@ inline int grid_for(int64_t n, int max_blocks = kMaxGrid) {
   return g;
 }
 
-// Grid of a pass that applies operator Op.
-template <class Op>
-inline int op_grid(int64_t n) { return grid_for(n, Op::kMaxBlocks); }
 
 }  // namespace its

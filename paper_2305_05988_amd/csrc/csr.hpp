@@ -56,12 +56,18 @@ struct CsrOp {
   // so any row length works.  The copy goes straight from memory to LDS
   // (global_load_lds, 16 bytes per lane) without passing through registers.
   static constexpr int kCap = 2048;
-  static constexpr int kMaxBlocks = kMaxGrid;
+
   struct Smem {
     V val[kCap + 16 / sizeof(V)];
     int32_t col[kCap + 4];
     int32_t rp[kBlock + 1];
   };
+
+  int grid() const { return grid_for(n); }
+  template <class Load, class Value, class Body>
+  __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
+    tiled_rows(*this, sm, load, value, body);
+  }
 
   template <class Fetch, class Consume>
   __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &sm, Fetch &&fetch,

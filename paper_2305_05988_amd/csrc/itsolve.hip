@@ -235,11 +235,13 @@ its_status with_op64(const its_matrix *A, F &&f) {
     case kSten7: {
       StencilOp<7, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 7; ++o) op.c[o] = A->coef[o];
+      op.plan();
       return f(op);
     }
     default: {
       StencilOp<27, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 27; ++o) op.c[o] = A->coef[o];
+      op.plan();
       return f(op);
     }
   }
@@ -259,12 +261,14 @@ its_status with_op32(const its_matrix *A, int dtype, F &&f) {
       StencilOp<7, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 7; ++o)
         op.c[o] = dtype == ITS_F32 ? float(A->coef[o]) : float(static_cast<_Float16>(A->coef[o]));
+      op.plan();
       return f(op);
     }
     default: {
       StencilOp<27, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 27; ++o)
         op.c[o] = dtype == ITS_F32 ? float(A->coef[o]) : float(static_cast<_Float16>(A->coef[o]));
+      op.plan();
       return f(op);
     }
   }
@@ -320,7 +324,7 @@ its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b,
   LAUNCH(run, kClassOther, k_dot, G, n, b, b, w.R);
   FINISH(run, 1, w.R, G, (FinDot{w.st, 0}));
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    const int GA = op_grid<decltype(op)>(n);
+    const int GA = op.grid();
     LAUNCH(run, kClassOther, k_residual<decltype(op)>, GA, op, b, x, r, rstride, w.R);
     FINISH(run, 1, w.R, GA, (FinDot{w.st, 1}));
     return ITS_OK;
@@ -341,7 +345,7 @@ double threshold2(double rtol, double bb) {
 its_status true_residual(Run &run, const its_matrix *A, const WS &w, const double *b,
                          const double *x, State *host, double bb, its_result *res) {
   its_status s = with_op64(A, [&](auto op) -> its_status {
-    const int GA = op_grid<decltype(op)>(A->n);
+    const int GA = op.grid();
     LAUNCH(run, kClassOther, k_residual<decltype(op)>, GA, op, b, x, (double *)nullptr, 1, w.R);
     FINISH(run, 1, w.R, GA, (FinDot{w.st2, 2}));
     return ITS_OK;
@@ -380,7 +384,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
-      const int GA = op_grid<decltype(op)>(n);
+      const int GA = op.grid();
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), GA, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
@@ -427,7 +431,7 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
-      const int GA = op_grid<decltype(op)>(n);
+      const int GA = op.grid();
       LAUNCH(run, kClassOther, k_cgnb_init<decltype(op)>, GA, op, ra, p, w.R);
       FINISH(run, 1, w.R, GA, (FinCgnbInit{w.st}));
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
@@ -478,7 +482,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   for (;; ++outer) {
     if (outer > 0) {  // r = b - A x of the refined iterate
       s = with_op64(A, [&](auto op) -> its_status {
-        const int GA = op_grid<decltype(op)>(n);
+        const int GA = op.grid();
         LAUNCH(run, 2, k_residual<decltype(op)>, GA, op, b, (const double *)x, r, 1, w.R);
         FINISH(run, 1, w.R, GA, (FinDot{w.st, 1}));
         return ITS_OK;
@@ -502,7 +506,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     if (!(rho_i <= ithr2)) {
       LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
       s = with_op32(A, dt, [&](auto op) -> its_status {
-        const int GA = op_grid<decltype(op)>(n);
+        const int GA = op.grid();
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
           LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
@@ -557,7 +561,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
     const double rt2 = o->restart_tol * o->restart_tol;
     const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
     s = with_op64(A, [&](auto op) -> its_status {
-      const int GA = op_grid<decltype(op)>(n);
+      const int GA = op.grid();
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         const int a = int(j & 1), c = a ^ 1;
         LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], (const State *)w.st, w.R);
@@ -605,7 +609,7 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
   LAUNCH(run, kClassOther, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
   // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
   s = with_op64(A, [&](auto op) -> its_status {
-    const int GA = op_grid<decltype(op)>(n);
+    const int GA = op.grid();
     return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
       LAUNCH(run, 0, k_jacobi<decltype(op)>, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
@@ -670,7 +674,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   };
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
-      const int GA = op_grid<decltype(op)>(n);
+      const int GA = op.grid();
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         for (int c = (j == 0 ? 0 : 1); c < nc; ++c) {
           its_status e = sweep(c);
@@ -1007,7 +1011,7 @@ its_status its_spmv(const its_matrix *A, const double *x, double *y, void *strea
   if (x == y) return fail(ITS_E_INVALID, "x and y alias");
   hipStream_t s = S(stream);
   its_status st = with_op64(A, [&](auto op) -> its_status {
-    const int grid = op_grid<decltype(op)>(A->n);
+    const int grid = op.grid();
     hipLaunchKernelGGL(k_spmv<decltype(op)>, dim3(grid), dim3(kBlock), 0, s, op, x, y);
     return ITS_OK;
   });

@@ -51,11 +51,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Op A, const double *__restrict_
                                                  double *__restrict__ y) {
   __shared__ typename Op::Smem sm;
   auto xj = [&](int32_t j) { return x[j]; };
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+  auto same = [](double v) { return v; };
+  A.rows(sm, xj, same, [&](int32_t i, bool valid, auto &&entries, auto &&) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double a, double v) { acc = fma(a, v, acc); });
-    const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) st_nt(y + i, acc);
+    entries([&](int32_t, double a, double v) { acc = fma(a, v, acc); });
+    if (valid) st_nt(y + i, acc);
   });
 }
 
@@ -67,12 +67,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restr
                                                      int rstride, Reduce *R) {
   __shared__ typename Op::Smem sm;
   auto xj = [&](int32_t j) { return x[j]; };
+  auto same = [](double v) { return v; };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+  A.rows(sm, xj, same, [&](int32_t i, bool valid, auto &&entries, auto &&) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
-    const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) {
+    entries([&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    if (valid) {
       const double ri = ld_nt(b + i) - acc;
       if (r) st_nt(r + int64_t(i) * rstride, ri);
       a.add(ri, ri);

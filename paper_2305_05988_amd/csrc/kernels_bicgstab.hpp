@@ -55,22 +55,19 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restric
     return RPV{r[j], po[j], vo[j]};
   };
   auto pv = [&](const RPV &e) -> double { return plain ? e.r : fma(bet, fma(-om, e.v, e.p), e.r); };
-  auto pj = [&](int32_t j) -> double { return pv(load(j)); };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    const int32_t i = r0 + int32_t(threadIdx.x);
+  A.rows(sm, load, pv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
     double acc = 0.0, pi = 0.0;
     bool have = false;  // p_i taken from the row's diagonal entry
-    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const RPV &e) {
-      const double p = pv(e);
+    entries([&](int32_t j, double av, double p) {
       acc = fma(av, p, acc);
       if (j == i) {
         pi = p;
         have = true;
       }
     });
-    if (i < r1) {
-      if (!have) pi = pj(i);
+    if (valid) {
+      if (!have) pi = own();
       st_nt(pn + i, pi);
       st_nt(vn + i, acc);
       double rsi;
@@ -118,22 +115,19 @@ __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restric
     return e;
   };
   auto sv = [&](const double2_t &e) -> double { return fma(-alpha, e.y, e.x); };
-  auto sj = [&](int32_t j) -> double { return sv(load(j)); };
   Dot2 a0, a1;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    const int32_t i = r0 + int32_t(threadIdx.x);
+  A.rows(sm, load, sv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
     double acc = 0.0, si = 0.0;
     bool have = false;  // s_i taken from the row's diagonal entry
-    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const double2_t &e) {
-      const double sv_j = sv(e);
+    entries([&](int32_t j, double av, double sv_j) {
       acc = fma(av, sv_j, acc);
       if (j == i) {
         si = sv_j;
         have = true;
       }
     });
-    if (i < r1) {
-      if (!have) si = sj(i);
+    if (valid) {
+      if (!have) si = own();
       st_nt(t + i, acc);
       a0.add(acc, si);
       a1.add(acc, acc);

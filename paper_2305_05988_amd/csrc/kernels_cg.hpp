@@ -29,21 +29,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
   auto load = [&](int32_t j) -> P2 { return rp[j]; };
   auto pv = [&](const P2 &v) -> T { return first ? v.x : fmaT(beta, v.y, v.x); };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    const int32_t i = r0 + int32_t(threadIdx.x);
+  A.rows(sm, load, pv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
     T acc = T(0), pi = T(0);
     bool have = false;  // p_i taken from the row's diagonal entry
-    A.tile_entries(r0, r1, sm, load, [&](int32_t j, T av, const P2 &v) {
-      const T pj = pv(v);
+    entries([&](int32_t j, T av, T pj) {
       acc = fmaT(av, pj, acc);
       if (j == i) {
         pi = pj;
         have = true;
       }
     });
-    if (i < r1) {
+    if (valid) {
       st_nt(q + i, acc);
-      if (!have) pi = pv(rp[i]);
+      if (!have) pi = own();
       a.add(double(pi), double(acc));
     }
   });

@@ -27,12 +27,12 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_init(Op A, double2_t *__restric
                                                       double *__restrict__ p, Reduce *R) {
   __shared__ typename Op::Smem sm;
   auto rj = [&](int32_t j) -> double { return ra[j].x; };
+  auto same = [](double v) { return v; };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+  A.rows(sm, rj, same, [&](int32_t i, bool valid, auto &&entries, auto &&) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, rj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
-    const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) {
+    entries([&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    if (valid) {
       const double ri = ra[i].x;
       st_nt(p + i, ri);
       a.add(acc, ri);
@@ -68,21 +68,19 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_x(Op A, const double2_t *__rest
   auto load = [&](int32_t j) -> double2_t { return ra[j]; };
   auto rv = [&](const double2_t &v) -> double { return fma(-alpha, v.y, v.x); };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    const int32_t i = r0 + int32_t(threadIdx.x);
+  A.rows(sm, load, rv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
     double acc = 0.0, ri = 0.0;
     bool have = false;  // r_i taken from the row's diagonal entry
-    A.tile_entries(r0, r1, sm, load, [&](int32_t j, double av, const double2_t &v) {
-      const double rj = rv(v);
+    entries([&](int32_t j, double av, double rj) {
       acc = fma(av, rj, acc);
       if (j == i) {
         ri = rj;
         have = true;
       }
     });
-    if (i < r1) {
+    if (valid) {
       st_nt(w + i, acc);
-      if (!have) ri = rv(ra[i]);
+      if (!have) ri = own();
       a.add(ri, ri);
     }
   });

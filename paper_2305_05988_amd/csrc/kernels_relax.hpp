@@ -18,18 +18,18 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restric
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   auto xj = [&](int32_t j) { return xo[j]; };
+  auto same = [](double v) { return v; };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
-    const int32_t i = r0 + int32_t(threadIdx.x);
+  A.rows(sm, xj, same, [&](int32_t i, bool valid, auto &&entries, auto &&) {
     double full = 0.0, off = 0.0, diag = 0.0;
-    A.tile_entries(r0, r1, sm, xj, [&](int32_t j, double av, double v) {
+    entries([&](int32_t j, double av, double v) {
       full = fma(av, v, full);
       if (j == i)
         diag = av;
       else
         off = fma(av, v, off);
     });
-    if (i < r1) {
+    if (valid) {
       const double bi = ld_nt(b + i);
       const double ri = bi - full;
       a.add(ri, ri);
@@ -107,12 +107,12 @@ __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restr
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   auto xj = [&](int32_t j) { return x[j]; };
+  auto same = [](double v) { return v; };
   Dot2 a;
-  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+  A.rows(sm, xj, same, [&](int32_t i, bool valid, auto &&entries, auto &&) {
     double acc = 0.0;
-    A.tile_entries(r0, r1, sm, xj, [&](int32_t, double av, double v) { acc = fma(av, v, acc); });
-    const int32_t i = r0 + int32_t(threadIdx.x);
-    if (i < r1) {
+    entries([&](int32_t, double av, double v) { acc = fma(av, v, acc); });
+    if (valid) {
       const double ri = b[i] - acc;
       a.add(ri, ri);
     }

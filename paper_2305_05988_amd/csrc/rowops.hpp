@@ -17,6 +17,15 @@
 // makes the compiler wait for each gather in turn; this way a thread keeps
 // the group's gathers in flight together while the chain itself stays
 // strictly sequential.
+//
+// Row sweep: the SpMV passes use rows(smem, load, value, body) instead.
+// body(i, valid, entries, own) is called by every thread of the block for
+// each row it owns (valid = false for slots past the last row); inside it,
+// entries(consume) calls consume(j, a_ij, x_j) for the row's entries in
+// stored order with x_j = value(load(j)), and own() returns x_i.  entries
+// must be called once per body call, by every thread (the CSR operator
+// synchronises the block inside it).  The CSR operators walk 1-D tiles; the
+// stencil operator marches 2-D tiles along z with the vector staged in LDS.
 #pragma once
 
 #include "common.hpp"
@@ -24,6 +33,22 @@
 namespace its {
 
 constexpr int kGather = 8;
+
+// rows() for the operators that walk 1-D tiles of kBlock rows.
+template <class Op, class Load, class Value, class Body>
+__device__ __forceinline__ void tiled_rows(const Op &A, typename Op::Smem &sm, Load &&load,
+                                           Value &&value, Body &&body) {
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    const int32_t i = r0 + int32_t(threadIdx.x);
+    auto entries = [&](auto &&consume) {
+      A.tile_entries(r0, r1, sm, load, [&](int32_t j, auto av, const auto &raw) {
+        consume(j, av, value(raw));
+      });
+    };
+    auto own = [&]() { return value(load(i)); };
+    body(i, i < r1, entries, own);
+  });
+}
 
 __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }

@@ -56,9 +56,13 @@ struct SellOp {
   const V *__restrict__ val;
   int32_t n;
 
-  static constexpr int kMaxBlocks = kMaxGrid;
-
   struct Smem {};
+
+  int grid() const { return grid_for(n); }
+  template <class Load, class Value, class Body>
+  __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
+    tiled_rows(*this, sm, load, value, body);
+  }
 
   // Entries g .. g + W - 1 of the lane's row in a slice of width w (g even):
   // all column and value loads, then all gathers, then the chain.  W is a
