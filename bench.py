@@ -233,6 +233,48 @@ def timed(fn, reps=1):
     return (time.perf_counter() - t0) / reps, out
 
 
+def ir_27pt(its, inputs, args, N=192):
+    """Mixed precision on the SPD 27-point (26, -1) CSR system at 192^3: values
+    stored in FP32 and separately in FP16, refinement to 1e-10 (error against
+    an FP64 CG solution to 1e-12 and against x*) and to 1e-8 (wall time
+    against FP64 CG to 1e-8)."""
+    import torch
+    t0 = time.perf_counter()
+    rp, col, val = inputs.stencil27_csr(N)
+    n, nnz = rp.size - 1, col.size
+    A = its.CSRMatrix.from_numpy(rp, col, val, lowp=("f32", "f16"), validate=False,
+                                 pack=args.layout == "packed")
+    del rp, col, val
+    xs = torch.from_numpy(inputs.uniform_vector(n, 1)).cuda()
+    b = its.spmv(A, xs)
+    torch.cuda.synchronize()
+    out = {"n": n, "nnz": nnz, "setup_s": time.perf_counter() - t0}
+    xref, iref = its.solve(A, b, method="cg", rtol=1e-12, max_iter=20000)
+    out["fp64_cg_1e-12_iters"] = iref.iters
+    its.solve(A, b, method="cg", rtol=1e-8, max_iter=20000)
+    t64, (x64, i64) = timed(lambda: its.solve(A, b, method="cg", rtol=1e-8, max_iter=20000))
+    out.update({"fp64_cg_1e-8_s": t64, "fp64_cg_1e-8_iters": i64.iters,
+                "fp64_cg_1e-8_iters_per_s": i64.iters / t64})
+    xn = xref.norm().item()
+    for lowp in ("f32", "f16"):
+        for rtol in (1e-8, 1e-10):
+            kw = dict(method="cg", rtol=rtol, max_iter=20000, inner_dtype=lowp, inner_rtol=1e-4)
+            its.solve(A, b, **kw)
+            t, (xl, il) = timed(lambda: its.solve(A, b, **kw))
+            key = f"ir_{lowp}_{rtol:g}"
+            out[f"{key}_s"] = t
+            out[f"{key}_outer"] = il.iters
+            out[f"{key}_inner"] = il.inner_iters
+            out[f"{key}_true_rel_res"] = il.true_rel_res
+            out[f"{key}_err_vs_fp64"] = (xl - xref).norm().item() / xn
+            out[f"{key}_err_vs_xstar"] = (xl - xs).norm().item() / xs.norm().item()
+            if rtol == 1e-8:
+                out[f"{key}_speedup_vs_fp64"] = t64 / t
+    log(f"ir 27-point {N}^3: {json.dumps(out)}")
+    del A, xs, b, xref, x64
+    return out
+
+
 def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     import torch
     ex = {}
@@ -300,6 +342,7 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
                                        "achieved_gbs": info.iters / t * (2 * M2 + 17 * 8 * n2) / 1e9,
                                        "true_rel_res": info.true_rel_res}
     del C, x2, b2, xb
+    ex["ir_27pt_192"] = ir_27pt(its, inputs, args)
     if args.layout == "packed":
         # the same CG solve with the matrix left in CSR (LDS-staged tiles)
         rp, col, val = inputs.poisson7_csr(N)
