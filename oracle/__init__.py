@@ -54,6 +54,10 @@ def load(path):
     L.orc_bicgstab.argtypes = [I64, P, P, P, P, P, D, I64, D, I32, P]
     L.orc_ir_cg.argtypes = [I64, P, P, P, P, P, P, D, I64, D, I64, P]
     L.orc_lu_solve.argtypes = [I64, P, P]
+    L.orc_varcoef_csr.restype = I64
+    L.orc_varcoef_csr.argtypes = [I32, I32, I32, P, P, P, P]
+    L.orc_varcoef_grad.restype = None
+    L.orc_varcoef_grad.argtypes = [I32, I32, I32, P, P, P, P]
     for f in ("orc_jacobi", "orc_sgs", "orc_cg", "orc_cgnb", "orc_bicgstab", "orc_ir_cg",
               "orc_lu_solve"):
         getattr(L, f).restype = C.c_int
@@ -203,3 +207,26 @@ def csr_to_dense(A) -> np.ndarray:
         for k in range(rp[i], rp[i + 1]):
             d[i, col[k]] += val[k]
     return d
+
+
+def varcoef_csr(nx, ny, nz, k):
+    """CSR (row_ptr int64, col int32, val float64) of the variable-coefficient
+    diffusion operator with per-cell coefficients k (harmonic face means,
+    boundary face = the cell's own k)."""
+    k = _f64(k)
+    n = nx * ny * nz
+    assert k.size == n
+    cap = 7 * n
+    rp = np.empty(n + 1, np.int64)
+    col = np.empty(max(cap, 1), np.int32)
+    val = np.empty(max(cap, 1), np.float64)
+    nnz = lib().orc_varcoef_csr(nx, ny, nz, _p(k), _p(rp), _p(col), _p(val))
+    return rp, col[:nnz].copy(), val[:nnz].copy()
+
+
+def varcoef_grad(nx, ny, nz, k, x, lam):
+    """dL/dk for A(k) x = b, given x and the adjoint lam (A lam = dL/dx)."""
+    k, x, lam = _f64(k), _f64(x), _f64(lam)
+    dk = np.empty(k.size, np.float64)
+    lib().orc_varcoef_grad(nx, ny, nz, _p(k), _p(x), _p(lam), _p(dk))
+    return dk

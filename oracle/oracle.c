@@ -768,3 +768,94 @@ int orc_lu_solve(int64_t n, double *a, double *b) {
   }
   return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Variable-coefficient diffusion (not in the paper, which uses constant     */
+/* stencils; it is the operator of the differentiable solve).                */
+/*                                                                           */
+/* Cell-centred finite volumes on nx*ny*nz, row i + nx(j + ny k), per-cell   */
+/* coefficient k_c > 0, homogeneous Dirichlet boundary:                      */
+/*   (A x)_c = sum over the 6 faces f of c of k_f (x_c - x_nbr),            */
+/* with x_nbr = 0 across the boundary.  An interior face between cells a and */
+/* b (a the lower row index) has the harmonic mean k_f = 2 k_a k_b/(k_a+k_b) */
+/* (flux continuity across two half-cells).  Reading: a boundary face has    */
+/* k_f = k_c (a ghost cell with the same coefficient), so k = 1 gives the   */
+/* (6, -1) Laplacian.  Roundings fixed here and matched by the GPU:          */
+/*   face:  ((2 a) b) / (a + b), a the lower-index cell;                     */
+/*   diagonal: 0 + f(z-1) + f(y-1) + f(x-1) + f(x+1) + f(y+1) + f(z+1),     */
+/*             left to right, boundary faces included;                       */
+/*   off-diagonal entry: -f; entries in ascending column order.             */
+/* ------------------------------------------------------------------------ */
+static double orc_face(double a, double b) { return (2.0 * a * b) / (a + b); }
+
+int64_t orc_varcoef_csr(int32_t nx, int32_t ny, int32_t nz, const double *k, int64_t *rp,
+                        int32_t *col, double *val) {
+  const int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  int64_t i, at = 0;
+  for (i = 0; i < n; i++) {
+    const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    /* faces in the order z-1, y-1, x-1, x+1, y+1, z+1 */
+    const int64_t off[6] = {-nxy, -nx, -1, 1, nx, nxy};
+    const int in[6] = {iz > 0, iy > 0, ix > 0, ix < nx - 1, iy < ny - 1, iz < nz - 1};
+    double f[6], diag = 0.0;
+    int o;
+    for (o = 0; o < 6; o++) {
+      if (!in[o])
+        f[o] = k[i];
+      else if (off[o] < 0)
+        f[o] = orc_face(k[i + off[o]], k[i]);
+      else
+        f[o] = orc_face(k[i], k[i + off[o]]);
+      diag = diag + f[o];
+    }
+    rp[i] = at;
+    for (o = 0; o < 3; o++)
+      if (in[o]) {
+        col[at] = (int32_t)(i + off[o]);
+        val[at++] = -f[o];
+      }
+    col[at] = (int32_t)i;
+    val[at++] = diag;
+    for (o = 3; o < 6; o++)
+      if (in[o]) {
+        col[at] = (int32_t)(i + off[o]);
+        val[at++] = -f[o];
+      }
+  }
+  rp[n] = at;
+  return at;
+}
+
+/* Gradient of L(x(k)) with respect to k where A(k) x = b and lam solves     */
+/* A^T lam = dL/dx (A is symmetric): dL/dk_c = -lam^T (dA/dk_c) x.  Face f of */
+/* c with neighbour m contributes dk_f/dk_c (lam_c - lam_m)(x_c - x_m), with  */
+/* dk_f/dk_c = 2 k_m^2/(k_c + k_m)^2; a boundary face (k_f = k_c, lam_m =     */
+/* x_m = 0) contributes lam_c x_c.  Roundings (matched by the GPU):           */
+/*   dk_f/dk_c = ((2 k_m) k_m) / ((k_c + k_m)(k_c + k_m));                    */
+/*   term = (dk_f/dk_c (lam_c - lam_m)) (x_c - x_m);                          */
+/*   dk_c = -(0 + term(z-1) + ... + term(z+1)), faces in the order above.     */
+void orc_varcoef_grad(int32_t nx, int32_t ny, int32_t nz, const double *k, const double *x,
+                      const double *lam, double *dk) {
+  const int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  int64_t i;
+  for (i = 0; i < n; i++) {
+    const int64_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int64_t off[6] = {-nxy, -nx, -1, 1, nx, nxy};
+    const int in[6] = {iz > 0, iy > 0, ix > 0, ix < nx - 1, iy < ny - 1, iz < nz - 1};
+    double acc = 0.0;
+    int o;
+    for (o = 0; o < 6; o++) {
+      double term;
+      if (!in[o]) {
+        term = lam[i] * x[i];
+      } else {
+        const int64_t m = i + off[o];
+        const double s = k[i] + k[m];
+        const double d = (2.0 * k[m] * k[m]) / (s * s);
+        term = (d * (lam[i] - lam[m])) * (x[i] - x[m]);
+      }
+      acc = acc + term;
+    }
+    dk[i] = -acc;
+  }
+}

@@ -67,6 +67,13 @@ int orc_ir_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *va
 
 int orc_lu_solve(int64_t n, double *a, double *b);
 
+/* variable-coefficient diffusion: CSR assembly (returns nnz; arrays sized for
+   the 7-point structure) and the adjoint gradient with respect to k */
+int64_t orc_varcoef_csr(int32_t nx, int32_t ny, int32_t nz, const double *k, int64_t *rp,
+                        int32_t *col, double *val);
+void orc_varcoef_grad(int32_t nx, int32_t ny, int32_t nz, const double *k, const double *x,
+                      const double *lam, double *dk);
+
 #ifdef __cplusplus
 }
 #endif

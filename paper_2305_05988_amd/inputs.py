@@ -152,3 +152,13 @@ def sine_mode(nx, ny, nz, growth=(1.0, 1.0, 1.0)) -> np.ndarray:
         return (g ** t) * np.sin(t * np.pi / (m + 1))
     vx, vy, vz = axis(nx, growth[0]), axis(ny, growth[1]), axis(nz, growth[2])
     return (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).ravel()
+
+
+def gaussian_field(n: int, seed, sigma=1.0) -> np.ndarray:
+    """i.i.d. N(0, sigma^2) per cell (a log-coefficient field g or theta)."""
+    return np.random.default_rng(seed).standard_normal(n) * sigma
+
+
+def diffusion_coefficients(g) -> np.ndarray:
+    """Per-cell diffusion coefficients k = exp(g)."""
+    return np.exp(np.asarray(g, dtype=np.float64))

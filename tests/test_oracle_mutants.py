@@ -13,6 +13,7 @@ from oracle import build as obuild
 
 from . import test_oracle_kernels as K
 from . import test_oracle_solvers as S
+from . import test_oracle_varcoef as V
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "oracle.c")
 
@@ -54,6 +55,18 @@ MUTANTS = [
      [K.test_spmv_is_an_fma_chain_in_stored_order]),
     ("ir update unscaled", "x[i] = fma(rn, (double)d[i], x[i]);", "x[i] = x[i] + (double)d[i];",
      [lambda: S.test_ir_cg_reaches_fp64_accuracy(S.np.float32)]),
+    ("varcoef face arithmetic mean", "return (2.0 * a * b) / (a + b);", "return 0.5 * (a + b);",
+     [lambda: V.test_operator_matches_face_flux_assembly((3, 3, 3))]),
+    ("varcoef boundary face doubled", "        f[o] = k[i];\n", "        f[o] = 2.0 * k[i];\n",
+     [V.test_unit_coefficients_give_the_poisson_matrix,
+      lambda: V.test_operator_matches_face_flux_assembly((4, 3, 2))]),
+    ("varcoef gradient drops the square", "const double d = (2.0 * k[m] * k[m]) / (s * s);",
+     "const double d = (2.0 * k[m]) / s;",
+     [lambda: V.test_gradient_matches_central_differences((3, 3, 2))]),
+    ("varcoef gradient drops boundary faces", "term = lam[i] * x[i];", "term = 0.0;",
+     [lambda: V.test_gradient_matches_central_differences((3, 3, 2))]),
+    ("varcoef gradient sign", "dk[i] = -acc;", "dk[i] = acc;",
+     [lambda: V.test_gradient_matches_central_differences((4, 2, 3))]),
 ]
 
 
