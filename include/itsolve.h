@@ -67,7 +67,10 @@ typedef struct {
   int32_t profile;      /* 0: off.  k >= 1: time every k-th launch of each
                            kernel class with HIP events on the stream and
                            report the timed launches in its_result */
-  int32_t reserved;
+  int32_t transpose;    /* 1: solve A^T x = b (stencil operators: offsets
+                           reflected; variable-coefficient diffusion is
+                           symmetric); ITS_E_UNSUPPORTED for CSR.  Used for
+                           the adjoint solve of a differentiable solve */
 } its_options;
 
 #define ITS_MAX_KERNEL_CLASSES 8
@@ -160,6 +163,31 @@ its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolo
    nx*ny*nz < 2^31. */
 its_status its_stencil_create(int32_t nx, int32_t ny, int32_t nz, int32_t npts,
                               const double *coef, its_matrix **out /* host, out */);
+
+/* Variable-coefficient diffusion (not in the paper, whose matrices are
+   constant stencils; the operator of the differentiable solve): cell-centred
+   finite volumes on nx*ny*nz (rows i + nx(j + ny k)), homogeneous Dirichlet
+   boundary, (A x)_c = sum over the 6 faces of c of k_f (x_c - x_nbr) with
+   x_nbr = 0 across the boundary; an interior face between rows a < b has
+   k_f = ((2 k_a) k_b) / (k_a + k_b), a boundary face k_f = k_c.  Diagonal
+   0 + f(z-1) + f(y-1) + f(x-1) + f(x+1) + f(y+1) + f(z+1) in that order,
+   off-diagonal entries -k_f.  A is symmetric positive definite for k > 0.
+   k: n float64, device, borrowed, positive and finite (not checked).
+   Jacobi, CG, CG-NB and BiCGStab apply; Gauss-Seidel and mixed precision
+   return ITS_E_UNSUPPORTED. */
+its_status its_varcoef_create(int32_t nx, int32_t ny, int32_t nz, const double *k,
+                              its_matrix **out /* host, out */);
+
+/* Gradient of a loss L(x) with respect to the per-cell coefficients of a
+   variable-coefficient operator, where A(k) x = b and lam solves
+   A lam = dL/dx (the adjoint solve; A is symmetric):
+     dk_c = -sum over faces f of c of dk_f/dk_c (lam_c - lam_m)(x_c - x_m),
+   dk_f/dk_c = ((2 k_m) k_m) / ((k_c + k_m)(k_c + k_m)), a boundary face
+   contributing lam_c x_c; terms added from 0 in the face order above, then
+   negated.  (dL/db = lam.)  x, lam, dk: n float64, device; dk must not alias
+   the inputs.  Enqueued on `stream`, not synchronised. */
+its_status its_varcoef_grad(const its_matrix *A, const double *x, const double *lam, double *dk,
+                            void *stream);
 
 its_status its_matrix_destroy(its_matrix *A);
 int64_t its_matrix_rows(const its_matrix *A);

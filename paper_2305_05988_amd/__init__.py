@@ -1,8 +1,10 @@
 """MI355X iterative sparse solvers: Jacobi, symmetric Gauss-Seidel, CG and
 BiCGStab on CSR or matrix-free 7/27-point stencils, with a mixed-precision
-refined CG.  Every step runs in the HIP library libitsolve.so (C ABI in
+refined CG, a CG-NB variant, and differentiable solves (adjoint gradients
+with respect to the right-hand side and to per-cell diffusion
+coefficients).  Every step runs in the HIP library libitsolve.so (C ABI in
 include/itsolve.h); this package only marshals torch tensors to it.
 """
-from .api import (CSRMatrix, SolveInfo, StencilMatrix, cast_values, dot, solve, spmv,  # noqa: F401
-                  stream_copy)
+from .api import (CSRMatrix, SolveInfo, StencilMatrix, VarCoefMatrix, cast_values,  # noqa: F401
+                  diffusion_solve, dot, solve, spmv, stencil_solve, stream_copy, varcoef_grad)
 from ._lib import ItsError  # noqa: F401

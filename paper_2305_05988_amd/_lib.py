@@ -23,7 +23,7 @@ EXPORTS = (
     "its_csr_set_colors", "its_stencil_create", "its_matrix_destroy", "its_matrix_rows",
     "its_spmv", "its_dot_workspace_size", "its_dot", "its_workspace_size", "its_solve",
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
-    "its_csr_pack", "its_csr_packed_slots",
+    "its_csr_pack", "its_csr_packed_slots", "its_varcoef_create", "its_varcoef_grad",
 )
 
 
@@ -32,7 +32,7 @@ class Options(C.Structure):
                 ("max_iter", C.c_int64), ("restart_tol", C.c_double),
                 ("check_every", C.c_int32), ("inner_dtype", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int64),
-                ("profile", C.c_int32), ("reserved", C.c_int32)]
+                ("profile", C.c_int32), ("transpose", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -62,6 +62,8 @@ def load(path: str = LIB_PATH):
         "its_csr_validate": (st, [P, I32, P]),
         "its_csr_set_lowp": (st, [P, P, I32]),
         "its_csr_pack": (st, [P, C.c_double, P]),
+        "its_varcoef_create": (st, [I32, I32, I32, P, P]),
+        "its_varcoef_grad": (st, [P, P, P, P, P]),
         "its_csr_packed_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),

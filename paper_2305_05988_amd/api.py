@@ -144,6 +144,32 @@ class StencilMatrix(_Matrix):
         self._h = h
 
 
+class VarCoefMatrix(_Matrix):
+    """Matrix-free variable-coefficient diffusion on nx*ny*nz with per-cell
+    coefficients k (float64 CUDA tensor of nx*ny*nz values, borrowed: this
+    object keeps it alive)."""
+
+    def __init__(self, nx, ny, nz, k):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.k = _vec(k, self.n, "k")
+        h = C.c_void_p()
+        L.check(L.lib().its_varcoef_create(self.nx, self.ny, self.nz, _ptr(self.k), C.byref(h)),
+                "its_varcoef_create")
+        self._h = h
+
+
+def varcoef_grad(A, x, lam, dk=None):
+    """dL/dk of a variable-coefficient operator given the solution x and the
+    adjoint lam (A lam = dL/dx)."""
+    x = _vec(x, A.n, "x")
+    lam = _vec(lam, A.n, "lam")
+    dk = torch.empty_like(x) if dk is None else _vec(dk, A.n, "dk")
+    L.check(L.lib().its_varcoef_grad(A.handle, _ptr(x), _ptr(lam), _ptr(dk), _stream()),
+            "its_varcoef_grad")
+    return dk
+
+
 def spmv(A, x, y=None):
     x = _vec(x, A.n, "x")
     y = torch.empty_like(x) if y is None else _vec(y, A.n, "y")
@@ -190,7 +216,8 @@ class SolveInfo:
 
 
 def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mode="cosine",
-            inner_dtype="f64", inner_rtol=1e-4, max_outer=30, check_every=0, profile=False):
+            inner_dtype="f64", inner_rtol=1e-4, max_outer=30, check_every=0, profile=False,
+            transpose=False):
     o = L.Options()
     L.lib().its_default_options(C.byref(o))
     o.method = _METHODS[method]
@@ -203,6 +230,7 @@ def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mo
     o.max_outer = max_outer
     o.check_every = check_every
     o.profile = int(profile)
+    o.transpose = int(bool(transpose))
     return o
 
 
@@ -229,3 +257,65 @@ def solve(A, b, x0=None, workspace=None, **opts):
     info = SolveInfo(_STATUS.get(st, str(st)), st, r.iters, r.inner_iters, r.restarts,
                      r.rel_res, r.true_rel_res, list(r.kernel_ms), list(r.kernel_launches))
     return x, info
+
+
+class _DiffusionSolve(torch.autograd.Function):
+    """x = A(k)^{-1} b for the variable-coefficient diffusion operator.
+    Backward: one adjoint solve A lam = dL/dx (A is symmetric), then
+    dL/db = lam and dL/dk from the gradient kernel.  Only x is kept for the
+    backward pass; the forward iterates are not stored."""
+
+    @staticmethod
+    def forward(ctx, k, b, shape, opts):
+        A = VarCoefMatrix(*shape, k.detach())
+        x, info = solve(A, b.detach(), **opts)
+        if info.status != "ok":
+            raise RuntimeError(f"forward solve did not converge: {info}")
+        ctx.save_for_backward(k, x)
+        ctx.shape, ctx.opts = shape, opts
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        k, x = ctx.saved_tensors
+        A = VarCoefMatrix(*ctx.shape, k.detach())
+        lam, info = solve(A, gx.contiguous(), **ctx.opts)
+        if info.status != "ok":
+            raise RuntimeError(f"adjoint solve did not converge: {info}")
+        dk = varcoef_grad(A, x, lam)
+        return dk, lam, None, None
+
+
+def diffusion_solve(k, b, shape, method="cg", rtol=1e-10, max_iter=20000, **opts):
+    """Differentiable solve of the variable-coefficient diffusion system
+    A(k) x = b on a grid of ``shape`` = (nx, ny, nz): gradients flow to the
+    per-cell coefficients k and to b."""
+    o = dict(method=method, rtol=rtol, max_iter=max_iter, **opts)
+    return _DiffusionSolve.apply(k, b, tuple(int(v) for v in shape), o)
+
+
+class _StencilSolve(torch.autograd.Function):
+    """x = A^{-1} b for a constant stencil (any method); backward solves
+    A^T lam = dL/dx with the reflected stencil (dL/db = lam)."""
+
+    @staticmethod
+    def forward(ctx, b, A, opts):
+        x, info = solve(A, b.detach(), **opts)
+        if info.status != "ok":
+            raise RuntimeError(f"forward solve did not converge: {info}")
+        ctx.A, ctx.opts = A, opts
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        lam, info = solve(ctx.A, gx.contiguous(), transpose=True, **ctx.opts)
+        if info.status != "ok":
+            raise RuntimeError(f"adjoint solve did not converge: {info}")
+        return lam, None, None
+
+
+def stencil_solve(A, b, method="bicgstab", rtol=1e-10, max_iter=20000, **opts):
+    """Differentiable solve with a constant-stencil operator: gradients flow
+    to b through the transposed (adjoint) solve."""
+    o = dict(method=method, rtol=rtol, max_iter=max_iter, **opts)
+    return _StencilSolve.apply(b, A, o)

@@ -17,7 +17,7 @@
 
 using namespace its;
 
-enum MatKind { kCsr = 0, kSten7 = 1, kSten27 = 2 };
+enum MatKind { kCsr = 0, kSten7 = 1, kSten27 = 2, kVar7 = 3 };
 
 struct its_matrix {
   int kind = kCsr;
@@ -28,6 +28,7 @@ struct its_matrix {
   const __half *val16 = nullptr;
   int32_t nx = 0, ny = 0, nz = 0;
   double coef[27] = {};
+  const double *kcoef = nullptr;  // variable-coefficient diffusion: per-cell k (borrowed)
   // Gauss-Seidel colouring (CSR): rows grouped by colour, owned
   int32_t ncolors = 0;
   int32_t *color_rows = nullptr;
@@ -238,6 +239,11 @@ its_status with_op64(const its_matrix *A, F &&f) {
       op.plan();
       return f(op);
     }
+    case kVar7: {
+      VarCoefOp op{A->nx, A->ny, A->nz, int32_t(A->n), A->kcoef};
+      op.plan();
+      return f(op);
+    }
     default: {
       StencilOp<27, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
       for (int o = 0; o < 27; ++o) op.c[o] = A->coef[o];
@@ -250,6 +256,7 @@ its_status with_op64(const its_matrix *A, F &&f) {
 template <class F>
 its_status with_op32(const its_matrix *A, int dtype, F &&f) {
   switch (A->kind) {
+    case kVar7: return fail(ITS_E_UNSUPPORTED, "mixed precision is not available for variable coefficients");
     case kCsr:
       if (dtype == ITS_F32) {
         if (A->sp) return f(SellOp<float, float>{A->sp, A->scol, A->sval32, int32_t(A->n)});
@@ -634,6 +641,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
+  if (A->kind == kVar7) return fail(ITS_E_UNSUPPORTED, "Gauss-Seidel is not available for variable coefficients");
   const int nc = A->kind == kCsr ? A->ncolors : (A->kind == kSten7 ? 2 : 8);
   double bb, rr;
   its_status s = prologue(run, A, w, b, x, nullptr, 1, h, bb, rr);
@@ -702,6 +710,10 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
 }
 
 its_status check_diag(Run &run, its_matrix *A, const WS &w) {
+  if (A->kind == kVar7) {  // diagonal = sum of positive face coefficients
+    A->diag_state = 1;
+    return ITS_OK;
+  }
   if (A->kind != kCsr) {
     A->diag_state = A->coef[A->kind == kSten7 ? 3 : 13] != 0.0 ? 1 : -1;
     return ITS_OK;
@@ -728,6 +740,7 @@ bool options_ok(const its_options *o, std::string &why) {
   if (!(o->inner_rtol >= 0.0) || !std::isfinite(o->inner_rtol)) { why = "inner_rtol must be finite and >= 0"; return false; }
   if (o->max_outer < 0) { why = "max_outer must be >= 0"; return false; }
   if (o->profile < 0) { why = "profile must be >= 0"; return false; }
+  if (o->transpose != 0 && o->transpose != 1) { why = "transpose must be 0 or 1"; return false; }
   return true;
 }
 
@@ -750,6 +763,7 @@ void its_default_options(its_options *o) {
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
   o->profile = 0;
+  o->transpose = 0;
 }
 
 const char *its_status_string(int32_t st) {
@@ -838,6 +852,39 @@ its_status its_matrix_destroy(its_matrix *A) {
 }
 
 int64_t its_matrix_rows(const its_matrix *A) { return A ? A->n : -1; }
+
+its_status its_varcoef_create(int32_t nx, int32_t ny, int32_t nz, const double *k,
+                              its_matrix **out) {
+  if (!out) return fail(ITS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (nx < 0 || ny < 0 || nz < 0) return fail(ITS_E_INVALID, "negative grid size");
+  const int64_t n = int64_t(nx) * ny * nz;
+  if (n >= (int64_t(1) << 31) - 1) return fail(ITS_E_UNSUPPORTED, "grid must have < 2^31 nodes");
+  if (n > 0 && !k) return fail(ITS_E_INVALID, "k is null");
+  its_matrix *A;
+  its_status s = new_matrix(&A);
+  if (s != ITS_OK) return s;
+  A->kind = kVar7;
+  A->n = n;
+  A->nx = nx;
+  A->ny = ny;
+  A->nz = nz;
+  A->kcoef = k;
+  *out = A;
+  return ITS_OK;
+}
+
+its_status its_varcoef_grad(const its_matrix *A, const double *x, const double *lam, double *dk,
+                            void *stream) {
+  if (!A || A->kind != kVar7) return fail(ITS_E_INVALID, "not a variable-coefficient operator");
+  if (A->n == 0) return ITS_OK;
+  if (!x || !lam || !dk) return fail(ITS_E_INVALID, "null vector");
+  if (dk == x || dk == lam || dk == A->kcoef) return fail(ITS_E_INVALID, "dk aliases an input");
+  VarCoefOp op{A->nx, A->ny, A->nz, int32_t(A->n), A->kcoef};
+  hipLaunchKernelGGL(k_varcoef_grad, dim3(grid_for(A->n)), dim3(kBlock), 0, S(stream), op, x, lam, dk);
+  HIP_TRY(hipGetLastError());
+  return ITS_OK;
+}
 
 its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
@@ -1065,6 +1112,23 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
                      void *workspace, size_t ws_bytes, void *stream, its_result *res) {
   its_matrix *A = const_cast<its_matrix *>(Ac);  // only cached validation state changes
   if (!A || !o || !res) return fail(ITS_E_INVALID, "null argument");
+  // A^T: a constant stencil with its offsets reflected (entry (i, i+d) of A^T
+  // is A's entry for offset -d, with the same grid truncation); the
+  // variable-coefficient operator is symmetric.
+  its_matrix At;
+  if (o->transpose == 1 && A->kind != kVar7) {
+    if (A->kind == kCsr) return fail(ITS_E_UNSUPPORTED, "transposed solves need a stencil operator");
+    At.kind = A->kind;
+    At.n = A->n;
+    At.nx = A->nx;
+    At.ny = A->ny;
+    At.nz = A->nz;
+    const int np = A->kind == kSten7 ? 7 : 27;
+    for (int q = 0; q < np; ++q) At.coef[q] = A->coef[np - 1 - q];
+    At.diag_state = A->diag_state;
+    At.host_state = A->host_state;
+    A = &At;
+  }
   std::string why;
   if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
   if (A->n > 0 && (!b || !x)) return fail(ITS_E_INVALID, "null vector");

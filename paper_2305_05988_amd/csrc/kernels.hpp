@@ -14,3 +14,4 @@
 #include "kernels_util.hpp"
 #include "sell.hpp"
 #include "stencil.hpp"
+#include "varcoef.hpp"

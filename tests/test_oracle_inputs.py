@@ -111,3 +111,20 @@ def test_seeded_vectors_reproducible():
     assert np.array_equal(a, b)
     assert a.min() >= -1 and a.max() < 1
     assert not np.array_equal(a, inputs.uniform_vector(1000, 2))
+
+
+@pytest.mark.parametrize("gen", ["convdiff7", "stencil27"])
+def test_reflected_stencil_is_the_transpose(gen):
+    # A^T of a constant stencil truncated at the grid boundary is the stencil
+    # with its offsets reflected: the adjoint solves rely on it
+    g = (5, 4, 3)
+    c = inputs.convdiff7() if gen == "convdiff7" else inputs.STENCIL27
+    n = int(np.prod(g))
+
+    def dense(csr):
+        rp, col, val = csr
+        return sp.csr_matrix((val, col, rp), shape=(n, n)).toarray()
+
+    A = dense(inputs.stencil_csr(*g, c))
+    At = dense(inputs.stencil_csr(*g, tuple(reversed(c))))
+    assert np.array_equal(A.T, At)
