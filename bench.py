@@ -275,6 +275,72 @@ def ir_27pt(its, inputs, args, N=192):
     return out
 
 
+def differentiation(its, inputs):
+    """Variable-coefficient diffusion on 128^3 (theta ~ N(0,1) seed 3, k =
+    exp(theta), x_target U[-1,1) seed 2, b U[-1,1) seed 1): CG forward to
+    1e-10, loss 0.5 ||x - x_target||^2, backward = adjoint CG to 1e-10 plus
+    the gradient kernel.  And the BiCGStab adjoint (solve with A^T) on 96^3
+    upwind convection-diffusion, Peclet 10."""
+    import torch
+    out = {}
+    N = 128
+    n = N ** 3
+    theta = torch.from_numpy(inputs.gaussian_field(n, 3)).cuda().requires_grad_(True)
+    xt = torch.from_numpy(inputs.uniform_vector(n, 2)).cuda()
+    b = torch.from_numpy(inputs.uniform_vector(n, 1)).cuda().requires_grad_(True)
+    A = its.VarCoefMatrix(N, N, N, torch.exp(theta.detach()))
+    x, fi = its.solve(A, b.detach(), method="cg", rtol=1e-10, max_iter=20000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, fi = its.solve(A, b.detach(), method="cg", rtol=1e-10, max_iter=20000)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lam, ai = its.solve(A, (x - xt).contiguous(), method="cg", rtol=1e-10, max_iter=20000)
+    dk = its.varcoef_grad(A, x, lam)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    # the same through torch.autograd (forward + backward)
+    t0 = time.perf_counter()
+    xa = its.diffusion_solve(torch.exp(theta), b, (N, N, N), rtol=1e-10)
+    L = 0.5 * ((xa - xt) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    t_auto = time.perf_counter() - t0
+    V = 8 * n
+    out["diff_varcoef_128"] = {
+        "forward_iters": fi.iters, "forward_s": t_fwd, "forward_iters_per_s": fi.iters / t_fwd,
+        "forward_achieved_gbs": fi.iters / t_fwd * 11 * V / 1e9,
+        "adjoint_iters": ai.iters, "backward_s": t_bwd, "autograd_forward_backward_s": t_auto,
+        "loss": L.item(), "grad_theta_norm": theta.grad.norm().item(),
+        "grad_b_norm": b.grad.norm().item(),
+        "grad_matches_direct": bool(torch.allclose(theta.grad, dk * torch.exp(theta.detach()),
+                                                   rtol=1e-12, atol=0.0))}
+    del A, x, lam, dk, xa, theta, b, xt
+    # BiCGStab adjoint on upwind convection-diffusion
+    M = 96
+    S = its.StencilMatrix(M, M, M, inputs.convdiff7())
+    bb = torch.from_numpy(inputs.uniform_vector(M ** 3, 1)).cuda().requires_grad_(True)
+    w = torch.from_numpy(inputs.uniform_vector(M ** 3, 2)).cuda()
+    its.solve(S, bb.detach(), method="bicgstab", rtol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xb = its.stencil_solve(S, bb, rtol=1e-10)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    (xb * w).sum().backward()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    _, fi = its.solve(S, bb.detach(), method="bicgstab", rtol=1e-10, max_iter=5000)
+    _, ai = its.solve(S, w, method="bicgstab", rtol=1e-10, max_iter=5000, transpose=True)
+    out["adjoint_bicgstab_96_upwind"] = {"forward_iters": fi.iters, "forward_s": t_f,
+                                         "adjoint_iters": ai.iters, "backward_s": t_b,
+                                         "adjoint_true_rel_res": ai.true_rel_res}
+    log(f"differentiation: {json.dumps(out)}")
+    return out
+
+
 def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     import torch
     ex = {}
@@ -343,6 +409,7 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
                                        "true_rel_res": info.true_rel_res}
     del C, x2, b2, xb
     ex["ir_27pt_192"] = ir_27pt(its, inputs, args)
+    ex.update(differentiation(its, inputs))
     if args.layout == "packed":
         # the same CG solve with the matrix left in CSR (LDS-staged tiles)
         rp, col, val = inputs.poisson7_csr(N)
