@@ -246,6 +246,60 @@ its_status its_stream_copy(const double *src, double *dst, int64_t n, void *stre
 const char *its_status_string(int32_t status);
 const char *its_last_error(void); /* message of this thread's last error */
 
+/* ------------------------------------------------------------ batched solve
+   Many independent variable-coefficient diffusion systems (the operator of
+   its_varcoef_create), each with nrhs right-hand sides, solved by FP64 CG per
+   (system, right-hand side) and advanced together.  The paper's experiments
+   solve one large system per run; the batch is this library's analogue of
+   choosing the task granularity (Section 3.2): an autotuner picks how many
+   tiles of a system one work item covers, by timing the SpMV pass on the
+   first solve.  Each (system, rhs) follows exactly the arithmetic of the
+   single-system CG (the same iterates, bit for bit) and stops on its own
+   test; m = check_every iterations (default 16) are captured in one HIP
+   graph that is replayed until every (system, rhs) has stopped.
+
+   Layout: the systems' cells are concatenated in system order; vectors
+   interleave the right-hand sides, value (cell g, rhs r) at g * nrhs + r. */
+typedef struct its_batch its_batch;
+
+typedef struct {
+  int32_t status;          /* ITS_OK if every (system, rhs) converged, else
+                              ITS_BREAKDOWN if any broke down, else
+                              ITS_NOT_CONVERGED */
+  int32_t tiles_per_item;  /* the autotuner's choice */
+  int32_t graph_iters;     /* m */
+  int32_t pad;
+  int64_t max_iters;       /* largest iteration count over (system, rhs) */
+  int64_t replays;         /* graph launches */
+  double tune_ms;          /* time of the autotuning (first solve) */
+  double solve_ms;         /* wall time of this solve */
+} its_batch_result;
+
+/* dims: host, 3 * nsys values (nx, ny, nz per system, each >= 1).  k: device,
+   the systems' per-cell coefficients concatenated (positive, finite); read
+   once here to form each cell's 7 coefficients (same roundings as
+   its_varcoef_create) into memory the handle owns, so k may be freed after.
+   nrhs: 1, 2, 4 or 8.  Synchronises `stream`. */
+its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, int32_t nrhs,
+                            void *stream, its_batch **out /* host, out */);
+its_status its_batch_destroy(its_batch *B);
+/* Total cells of the batch (vectors hold cells * nrhs values); -1 if null. */
+int64_t its_batch_cells(const its_batch *B);
+/* Bytes of device workspace its_batch_solve needs (256-byte aligned). */
+size_t its_batch_workspace_size(const its_batch *B);
+/* Solves every (system, rhs) with FP64 CG (opts: method ITS_CG, inner_dtype
+   ITS_F64, rtol, max_iter per (system, rhs), check_every = m).  b, x: device,
+   cells * nrhs float64 (x: x0 in, solution out); b = 0 for a (system, rhs)
+   gives x = 0.  iters, status: optional host arrays of nsys * nrhs entries
+   (index s * nrhs + r) for the per-(system, rhs) iteration counts and
+   ITS_OK / ITS_NOT_CONVERGED / ITS_BREAKDOWN.  Runs on the handle's own
+   stream, ordered after the work already on `stream`, and returns when
+   done.  One solve per handle at a time. */
+its_status its_batch_solve(its_batch *B, const its_options *opts, const double *b, double *x,
+                           void *workspace, size_t ws_bytes, void *stream,
+                           its_batch_result *res /* host, out */, int64_t *iters,
+                           int32_t *status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,6 @@ with respect to the right-hand side and to per-cell diffusion
 coefficients).  Every step runs in the HIP library libitsolve.so (C ABI in
 include/itsolve.h); this package only marshals torch tensors to it.
 """
-from .api import (CSRMatrix, SolveInfo, StencilMatrix, VarCoefMatrix, cast_values,  # noqa: F401
+from .api import (Batch, CSRMatrix, SolveInfo, StencilMatrix, VarCoefMatrix, cast_values,  # noqa: F401
                   diffusion_solve, dot, solve, spmv, stencil_solve, stream_copy, varcoef_grad)
 from ._lib import ItsError  # noqa: F401

@@ -24,6 +24,8 @@ EXPORTS = (
     "its_spmv", "its_dot_workspace_size", "its_dot", "its_workspace_size", "its_solve",
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
     "its_csr_pack", "its_csr_packed_slots", "its_varcoef_create", "its_varcoef_grad",
+    "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
+    "its_batch_solve",
 )
 
 
@@ -41,6 +43,12 @@ class Result(C.Structure):
                 ("true_rel_res", C.c_double),
                 ("kernel_ms", C.c_double * MAX_KERNEL_CLASSES),
                 ("kernel_launches", C.c_int64 * MAX_KERNEL_CLASSES)]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("tiles_per_item", C.c_int32),
+                ("graph_iters", C.c_int32), ("pad", C.c_int32), ("max_iters", C.c_int64),
+                ("replays", C.c_int64), ("tune_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
 class ItsError(RuntimeError):
@@ -64,6 +72,11 @@ def load(path: str = LIB_PATH):
         "its_csr_pack": (st, [P, C.c_double, P]),
         "its_varcoef_create": (st, [I32, I32, I32, P, P]),
         "its_varcoef_grad": (st, [P, P, P, P, P]),
+        "its_batch_create": (st, [I32, P, P, I32, P, P]),
+        "its_batch_destroy": (st, [P]),
+        "its_batch_cells": (I64, [P]),
+        "its_batch_workspace_size": (SZ, [P]),
+        "its_batch_solve": (st, [P, P, P, P, P, SZ, P, P, P, P]),
         "its_csr_packed_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),

@@ -319,3 +319,66 @@ def stencil_solve(A, b, method="bicgstab", rtol=1e-10, max_iter=20000, **opts):
     to b through the transposed (adjoint) solve."""
     o = dict(method=method, rtol=rtol, max_iter=max_iter, **opts)
     return _StencilSolve.apply(b, A, o)
+
+
+@dataclass
+class BatchInfo:
+    status: str
+    iters: np.ndarray       # [nsys, nrhs]
+    statuses: np.ndarray    # [nsys, nrhs] ITS_OK / ITS_NOT_CONVERGED / ITS_BREAKDOWN
+    tiles_per_item: int
+    graph_iters: int
+    max_iters: int
+    replays: int
+    tune_ms: float
+    solve_ms: float
+
+
+class Batch:
+    """Many variable-coefficient diffusion systems (dims: sequence of
+    (nx, ny, nz)) with nrhs right-hand sides each, solved together by FP64 CG
+    per (system, rhs).  k: float64 CUDA tensor of the systems' per-cell
+    coefficients concatenated.  Vectors hold cells * nrhs values, (cell g,
+    rhs r) at g * nrhs + r."""
+
+    def __init__(self, dims, k, nrhs):
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
+        self.dims = d
+        self.nsys, self.nrhs = d.shape[0], int(nrhs)
+        self.cells = int(np.sum(np.prod(d.astype(np.int64), axis=1)))
+        _vec(k, self.cells, "k")
+        h = C.c_void_p()
+        L.check(L.lib().its_batch_create(self.nsys, d.ctypes.data_as(C.c_void_p), _ptr(k),
+                                         self.nrhs, _stream(), C.byref(h)), "its_batch_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and L._lib is not None:
+            L._lib.its_batch_destroy(self._h)
+            self._h = None
+
+    def offsets(self):
+        """First cell of each system."""
+        n = np.prod(self.dims.astype(np.int64), axis=1)
+        return np.concatenate([[0], np.cumsum(n)[:-1]])
+
+    def solve(self, b, x0=None, rtol=1e-8, max_iter=10000, check_every=0):
+        n = self.cells * self.nrhs
+        b = _vec(b, n, "b")
+        x = torch.zeros_like(b) if x0 is None else _vec(x0, n, "x0").clone()
+        nb = L.lib().its_batch_workspace_size(self._h)
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=b.device)
+        o = options(method="cg", rtol=rtol, max_iter=max_iter, check_every=check_every)
+        r = L.BatchResult()
+        iters = np.zeros(self.nsys * self.nrhs, np.int64)
+        stats = np.zeros(self.nsys * self.nrhs, np.int32)
+        st = L.check(L.lib().its_batch_solve(self._h, C.byref(o), _ptr(b), _ptr(x), _ptr(self._ws),
+                                             self._ws.numel(), _stream(), C.byref(r),
+                                             iters.ctypes.data_as(C.c_void_p),
+                                             stats.ctypes.data_as(C.c_void_p)), "its_batch_solve")
+        info = BatchInfo(_STATUS.get(st, str(st)), iters.reshape(self.nsys, self.nrhs),
+                         stats.reshape(self.nsys, self.nrhs), r.tiles_per_item, r.graph_iters,
+                         r.max_iters, r.replays, r.tune_ms, r.solve_ms)
+        return x, info

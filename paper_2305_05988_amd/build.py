@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libitsolve.so")
-SOURCES = [os.path.join(HERE, "csrc", "itsolve.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "itsolve.hip"), os.path.join(HERE, "csrc", "batch.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "host.hpp"
 #include "kernels.hpp"
 
 using namespace its;
@@ -63,10 +64,11 @@ static void free_packed(its_matrix *A) {
 
 static thread_local std::string g_err;
 
-static its_status fail(its_status st, const std::string &msg) {
+its_status its_fail(its_status st, const std::string &msg) {
   g_err = msg;
   return st;
 }
+static its_status fail(its_status st, const std::string &msg) { return its_fail(st, msg); }
 
 #define HIP_TRY(expr)                                                                    \
   do {                                                                                   \

@@ -162,3 +162,22 @@ def gaussian_field(n: int, seed, sigma=1.0) -> np.ndarray:
 def diffusion_coefficients(g) -> np.ndarray:
     """Per-cell diffusion coefficients k = exp(g)."""
     return np.exp(np.asarray(g, dtype=np.float64))
+
+
+def batch_systems(nsys: int, nrhs: int, seed=4, side_lo=16, side_hi=64, sigma=1.0):
+    """Uneven variable-coefficient systems for the batched solve: system s
+    draws its three grid sides from U{side_lo..side_hi}, then a N(0, sigma^2)
+    log-coefficient per cell, then nrhs right-hand sides U[-1, 1) per cell,
+    all from default_rng([seed, s]).  Returns (dims [nsys, 3], k concatenated
+    over the systems, b [cells, nrhs] with the right-hand sides of a cell
+    adjacent)."""
+    dims, ks, bs = [], [], []
+    for s in range(nsys):
+        rng = np.random.default_rng([seed, s])
+        d = rng.integers(side_lo, side_hi + 1, size=3)
+        n = int(np.prod(d))
+        dims.append(d)
+        ks.append(np.exp(rng.standard_normal(n) * sigma))
+        bs.append(rng.uniform(-1.0, 1.0, size=(n, nrhs)))
+    return (np.array(dims, dtype=np.int32), np.concatenate(ks),
+            np.concatenate(bs).astype(np.float64))

@@ -75,4 +75,11 @@ def test_host_side_argument_errors(lib):
     assert lib.its_matrix_destroy(P0) == L.ITS_OK
     assert lib.its_matrix_rows(P0) == -1
     assert lib.its_csr_pack(P0, 1.2, P0) == L.ITS_E_INVALID
+    dims = (C.c_int32 * 3)(4, 4, 4)
+    assert lib.its_batch_create(1, dims, C.c_void_p(8), 3, P0, C.byref(h)) == L.ITS_E_UNSUPPORTED
+    bad_dims = (C.c_int32 * 3)(4, 0, 4)
+    assert lib.its_batch_create(1, bad_dims, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
+    assert lib.its_batch_create(0, dims, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
+    assert lib.its_batch_cells(P0) == -1 and lib.its_batch_workspace_size(P0) == 0
+    assert lib.its_batch_destroy(P0) == L.ITS_OK
     assert lib.its_csr_packed_slots(P0) == 0

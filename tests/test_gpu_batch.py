@@ -1,0 +1,121 @@
+"""GPU parity of the batched solve: every (system, right-hand side) against
+the oracle's CG on that system's CSR matrix (variable coefficients), with the
+same right-hand side.  Bars: iterates bit-identical at fixed k; converged
+iteration counts equal and solutions within 1e-10; graph replays of
+different lengths and repeated solves give identical bits."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_05988_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def its():
+    import paper_2305_05988_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _batch(nsys, nrhs, lo=2, hi=9, seed=14):
+    dims, k, b = inputs.batch_systems(nsys, nrhs, seed=seed, side_lo=lo, side_hi=hi)
+    return dims, k, b, its().Batch(dims, dev(k), nrhs)
+
+
+def _oracle_each(dims, k, b, fn):
+    """fn(A_csr, b_col) -> result per (system, rhs)."""
+    out = []
+    off = 0
+    for d in dims:
+        n = int(np.prod(d))
+        A = oracle.varcoef_csr(*[int(v) for v in d], k[off:off + n])
+        out.append([fn(A, b[off:off + n, r]) for r in range(b.shape[1])])
+        off += n
+    return out
+
+
+def _split(x, dims, nrhs):
+    x = x.reshape(-1, nrhs)
+    off, parts = 0, []
+    for d in dims:
+        n = int(np.prod(d))
+        parts.append(x[off:off + n])
+        off += n
+    return parts
+
+
+@pytest.mark.parametrize("nrhs", [1, 4, 8])
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_batch_fixed_k_bit_exact(nrhs, k):
+    dims, kc, b, B = _batch(7, nrhs)
+    x, info = B.solve(dev(b.ravel()), rtol=0.0, max_iter=k)
+    ref = _oracle_each(dims, kc, b, lambda A, bb: oracle.cg(A, bb, rtol=0.0, max_iter=k)[0])
+    assert info.status == "not_converged" and np.all(info.iters == k)
+    for s, part in enumerate(_split(host(x), dims, nrhs)):
+        for r in range(nrhs):
+            assert np.array_equal(part[:, r], ref[s][r]), (s, r)
+
+
+def test_batch_converged_matches_oracle_per_system():
+    nrhs = 4
+    dims, kc, b, B = _batch(9, nrhs, lo=3, hi=12, seed=15)
+    b[:, 2] *= 1e3  # right-hand sides of different scales
+    x, info = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=5000)
+    ref = _oracle_each(dims, kc, b, lambda A, bb: oracle.cg(A, bb, rtol=1e-8, max_iter=5000))
+    assert info.status == "ok"
+    for s, part in enumerate(_split(host(x), dims, nrhs)):
+        for r in range(nrhs):
+            xr, rr = ref[s][r]
+            assert rr.status == oracle.OK and info.iters[s, r] == rr.iters, (s, r)
+            assert np.max(np.abs(part[:, r] - xr)) <= 1e-10 * np.max(np.abs(xr))
+    assert len(set(info.iters.ravel().tolist())) > 1  # systems stop at different counts
+
+
+def test_batch_zero_rhs_and_cap():
+    nrhs = 2
+    dims, kc, b, B = _batch(5, nrhs, lo=4, hi=8, seed=16)
+    b[:int(np.prod(dims[0])), 1] = 0.0  # system 0, rhs 1: b = 0
+    x0 = dev(np.ones(b.size))
+    x, info = B.solve(dev(b.ravel()), x0=x0, rtol=1e-12, max_iter=4)
+    part = _split(host(x), dims, nrhs)[0]
+    assert info.iters[0, 1] == 0 and info.statuses[0, 1] == 0 and not part[:, 1].any()
+    others = np.delete(info.statuses.ravel(), 1)
+    assert np.all(others == 1) and info.status == "not_converged"
+
+
+def test_batch_graph_length_and_repeated_solves_agree():
+    nrhs = 8
+    dims, kc, b, B = _batch(6, nrhs, lo=3, hi=10, seed=17)
+    bt = dev(b.ravel())
+    runs = []
+    for m in (1, 5, 16, 16):
+        x, info = B.solve(bt, rtol=1e-9, max_iter=3000, check_every=m)
+        runs.append((host(x), info.iters.copy()))
+        assert info.status == "ok" and info.graph_iters == m
+    for xr, it in runs[1:]:
+        assert np.array_equal(xr, runs[0][0]) and np.array_equal(it, runs[0][1])
+    # a different right-hand side through the cached graph
+    x2, info2 = B.solve(dev(2.0 * b.ravel()), rtol=1e-9, max_iter=3000, check_every=16)
+    ref = _oracle_each(dims, kc, 2.0 * b, lambda A, bb: oracle.cg(A, bb, rtol=1e-9, max_iter=3000))
+    for s, part in enumerate(_split(host(x2), dims, nrhs)):
+        for r in range(nrhs):
+            assert info2.iters[s, r] == ref[s][r][1].iters
+            assert np.max(np.abs(part[:, r] - ref[s][r][0])) <= 1e-10 * np.max(np.abs(ref[s][r][0]))
+
+
+def test_batch_autotuner_reports_its_choice():
+    dims, kc, b, B = _batch(4, 8, lo=8, hi=16, seed=18)
+    x, info = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
+    assert info.tiles_per_item in (1, 2, 4, 8, 16, 32) and info.tune_ms > 0
+    x, info2 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
+    assert info2.tiles_per_item == info.tiles_per_item and info2.tune_ms == info.tune_ms
