@@ -275,6 +275,45 @@ def ir_27pt(its, inputs, args, N=192):
     return out
 
 
+def batched(its, inputs, nsys=512, nrhs=8):
+    """512 variable-coefficient 7-point systems, sides U{16..64} per axis,
+    g ~ N(0, 1) per cell, k = exp(g), 8 right-hand sides U[-1, 1) each
+    (default_rng([4, s]) per system), FP64 CG to 1e-8 per (system, rhs) in
+    one graph-captured batch.  The first solve includes the autotuning; the
+    second is timed."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    dims, k, b = inputs.batch_systems(nsys, nrhs, seed=4)
+    n_s = np.prod(dims.astype(np.int64), axis=1)
+    B = its.Batch(dims, torch.from_numpy(k).cuda(), nrhs)
+    bt = torch.from_numpy(b.ravel()).cuda()
+    del b, k
+    setup = time.perf_counter() - t0
+    x, first = B.solve(bt, rtol=1e-8, max_iter=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = B.solve(bt, rtol=1e-8, max_iter=20000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = info.iters
+    # bytes actually needed: per (system, rhs) iteration 10 vector touches of 8 B per cell;
+    # per system iteration the 7 coefficients (56 B per cell) once for all right-hand sides
+    vec_bytes = float(np.sum(it * n_s[:, None]) * 80)
+    coef_bytes = float(np.sum(it.max(axis=1) * n_s) * 56)
+    out = {"systems": nsys, "rhs": nrhs, "cells": int(n_s.sum()), "setup_s": setup,
+           "status": info.status, "solve_s": dt, "first_solve_s": first.solve_ms / 1e3,
+           "tune_ms": first.tune_ms, "tiles_per_item": info.tiles_per_item,
+           "graph_iters": info.graph_iters, "replays": info.replays,
+           "iters_max": int(it.max()), "iters_mean": float(it.mean()), "iters_min": int(it.min()),
+           "solves_per_s": nsys * nrhs / dt,
+           "cell_rhs_iters_per_s": float(np.sum(it * n_s[:, None])) / dt,
+           "achieved_gbs": (vec_bytes + coef_bytes) / dt / 1e9}
+    log(f"batched: {json.dumps(out)}")
+    del B, bt, x
+    return out
+
+
 def differentiation(its, inputs):
     """Variable-coefficient diffusion on 128^3 (theta ~ N(0,1) seed 3, k =
     exp(theta), x_target U[-1,1) seed 2, b U[-1,1) seed 1): CG forward to
@@ -410,6 +449,7 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     del C, x2, b2, xb
     ex["ir_27pt_192"] = ir_27pt(its, inputs, args)
     ex.update(differentiation(its, inputs))
+    ex["batched_512x8_varcoef"] = batched(its, inputs)
     if args.layout == "packed":
         # the same CG solve with the matrix left in CSR (LDS-staged tiles)
         rp, col, val = inputs.poisson7_csr(N)
