@@ -275,6 +275,32 @@ def ir_27pt(its, inputs, args, N=192):
     return out
 
 
+def small32(its, inputs, N=32):
+    """The 32^3 Poisson CSR system (packed), where launches and reductions
+    rather than HBM set the pace: time to solution of each method to 1e-8
+    (Jacobi capped at 2000 sweeps), median of 5."""
+    import statistics
+    import torch
+    rp, col, val = inputs.poisson7_csr(N)
+    n = rp.size - 1
+    A = its.CSRMatrix.from_numpy(rp, col, val, pack=True, max_fill=2.0)
+    A.set_colors(inputs.redblack_colors(N, N, N), 2)
+    b = its.spmv(A, torch.from_numpy(inputs.uniform_vector(n, 1)).cuda())
+    out = {}
+    for method, cap in (("cg", 5000), ("bicgstab", 5000), ("cgnb", 5000), ("jacobi", 2000),
+                        ("sgs", 5000)):
+        its.solve(A, b, method=method, rtol=1e-8, max_iter=cap)
+        ts = []
+        for _ in range(5):
+            t, (x, info) = timed(lambda: its.solve(A, b, method=method, rtol=1e-8, max_iter=cap))
+            ts.append(t)
+        t = statistics.median(ts)
+        out[method] = {"iters": info.iters, "status": info.status, "s": t,
+                       "iters_per_s": info.iters / t}
+    log(f"32^3: {json.dumps(out)}")
+    return out
+
+
 def batched(its, inputs, nsys=512, nrhs=8):
     """512 variable-coefficient 7-point systems, sides U{16..64} per axis,
     g ~ N(0, 1) per cell, k = exp(g), 8 right-hand sides U[-1, 1) each
@@ -450,6 +476,7 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     ex["ir_27pt_192"] = ir_27pt(its, inputs, args)
     ex.update(differentiation(its, inputs))
     ex["batched_512x8_varcoef"] = batched(its, inputs)
+    ex["small_32"] = small32(its, inputs)
     if args.layout == "packed":
         # the same CG solve with the matrix left in CSR (LDS-staged tiles)
         rp, col, val = inputs.poisson7_csr(N)
