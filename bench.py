@@ -448,6 +448,11 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=5)
     t, (xg, info) = timed(lambda: its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=200))
     ex["rbsgs_256_stencil"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t}
+    # red-black symmetric Gauss-Seidel on the CSR matrix (colour-packed half-sweeps)
+    A.set_colors(inputs.redblack_colors(N, N, N), 2)
+    its.solve(A, b, method="sgs", rtol=args.rtol, max_iter=5)
+    t, (xg, info) = timed(lambda: its.solve(A, b, method="sgs", rtol=args.rtol, max_iter=100))
+    ex["rbsgs_256_csr"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t}
     # stream copy: achievable bandwidth
     src = torch.empty(n * 8, dtype=torch.float64, device="cuda").uniform_()
     dst = torch.empty_like(src)

@@ -44,7 +44,24 @@ struct its_matrix {
   float *sval32 = nullptr;
   __half *sval16 = nullptr;
   int64_t sell_entries = 0;
+  double pack_fill = 0.0;  // max_fill of the last its_csr_pack (0: not packed)
+  // Gauss-Seidel: each colour's rows packed the same way, in colour order
+  struct ColorPack {
+    int64_t *sp = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+  };
+  std::vector<ColorPack> cpack;
 };
+
+static void free_color_packs(its_matrix *A) {
+  for (auto &c : A->cpack) {
+    if (c.sp) (void)hipFree(c.sp);
+    if (c.col) (void)hipFree(c.col);
+    if (c.val) (void)hipFree(c.val);
+  }
+  A->cpack.clear();
+}
 
 static void free_packed(its_matrix *A) {
   if (A->sp) (void)hipFree(A->sp);
@@ -58,6 +75,8 @@ static void free_packed(its_matrix *A) {
   A->sval32 = nullptr;
   A->sval16 = nullptr;
   A->sell_entries = 0;
+  A->pack_fill = 0.0;
+  free_color_packs(A);
 }
 
 // ------------------------------------------------------------------ errors
@@ -670,6 +689,11 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
     if (A->kind == kCsr) {
       const int32_t beg = A->color_off[c], cnt = A->color_off[c + 1] - beg;
       if (cnt == 0) return ITS_OK;
+      if (!A->cpack.empty()) {
+        const auto &cp = A->cpack[size_t(c)];
+        LAUNCH(run, 0, k_gs_rows_packed, grid_for(cnt), SellOp<double, double>{cp.sp, cp.col, cp.val, cnt}, (const int32_t *)(A->color_rows + beg), b, x, (const State *)w.st);
+        return ITS_OK;
+      }
       LAUNCH(run, 0, k_gs_rows_csr, grid_for(cnt), CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, (const State *)w.st);
     } else if (A->kind == kSten7) {
       StencilOp<7, double> op{A->nx, A->ny, A->nz, n, {}};
@@ -932,21 +956,37 @@ struct DevTmp {  // device allocation freed on scope exit
 };
 }  // namespace
 
-its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
-  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
-  if (!(max_fill >= 1.0) || !std::isfinite(max_fill))
-    return fail(ITS_E_INVALID, "max_fill must be finite and >= 1");
-  free_packed(A);
-  const int64_t n = A->n, ns = (n + kSlice - 1) / kSlice;
-  if (n == 0) return ITS_OK;
-  hipStream_t s = S(stream);
+// Packs rows rows[0 .. count) (all rows in order when rows is null) of a CSR
+// matrix into the sliced layout; lowp also packs the low-precision values.
+// On success the new arrays are returned in out (owned by the caller).
+struct PackOut {
+  int64_t *sp = nullptr;
+  int32_t *col = nullptr;
+  double *val = nullptr;
+  float *val32 = nullptr;
+  __half *val16 = nullptr;
+  int64_t slots = 0;
+  void release() {
+    if (sp) (void)hipFree(sp);
+    if (col) (void)hipFree(col);
+    if (val) (void)hipFree(val);
+    if (val32) (void)hipFree(val32);
+    if (val16) (void)hipFree(val16);
+    *this = PackOut();
+  }
+};
+
+static its_status pack_rows(const its_matrix *A, const int32_t *rows, int64_t count, double max_fill,
+                            bool lowp, hipStream_t s, PackOut &out) {
+  const int64_t ns = (count + kSlice - 1) / kSlice;
+  if (count == 0) return ITS_OK;
   DevTmp width, bad;
   HIP_TRY(hipMalloc(&width.p, size_t(ns) * sizeof(int32_t)));
   HIP_TRY(hipMalloc(&bad.p, sizeof(uint32_t)));
   HIP_TRY(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
   const int gw = int(std::min<int64_t>((ns + kBlock - 1) / kBlock, 65536));
-  hipLaunchKernelGGL(k_sell_width, dim3(gw), dim3(kBlock), 0, s, int32_t(n), int32_t(A->nnz), A->rp,
-                     static_cast<int32_t *>(width.p), static_cast<uint32_t *>(bad.p));
+  hipLaunchKernelGGL(k_sell_width, dim3(gw), dim3(kBlock), 0, s, int32_t(count), int32_t(A->nnz), A->rp,
+                     rows, static_cast<int32_t *>(width.p), static_cast<uint32_t *>(bad.p));
   HIP_TRY(hipGetLastError());
   std::vector<int32_t> hw(static_cast<size_t>(ns));
   uint32_t hbad = 0;
@@ -957,52 +997,105 @@ its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
   std::vector<int64_t> hsp(static_cast<size_t>(ns) + 1, 0);
   for (int64_t q = 0; q < ns; ++q) hsp[size_t(q) + 1] = hsp[size_t(q)] + int64_t(kSlice) * hw[size_t(q)];
   const int64_t total = hsp[size_t(ns)];
-  // slots of the real rows (the rows past n in the last slice do not count)
+  // slots of the real rows (the positions past count in the last slice do
+  // not count) against the entries of those rows
   int64_t row_slots = 0;
-  for (int64_t q = 0; q < ns; ++q)
-    row_slots += std::min<int64_t>(kSlice, n - q * kSlice) * hw[size_t(q)];
-  if (double(row_slots) > max_fill * double(A->nnz) + kSlice)
+  for (int64_t q = 0; q < ns; ++q) row_slots += std::min<int64_t>(kSlice, count - q * kSlice) * hw[size_t(q)];
+  int64_t entries = A->nnz;
+  if (rows) {
+    entries = 0;  // the rows' own entries: the widths bound them from above
+    std::vector<int32_t> hr(static_cast<size_t>(count));
+    std::vector<int32_t> hrp(static_cast<size_t>(A->n) + 1);
+    HIP_TRY(hipMemcpyAsync(hr.data(), rows, size_t(count) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hrp.data(), A->rp, size_t(A->n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t i : hr) entries += hrp[size_t(i) + 1] - hrp[size_t(i)];
+  }
+  if (double(row_slots) > max_fill * double(entries) + kSlice)
     return fail(ITS_E_UNSUPPORTED, "row lengths vary too much: the packed rows would hold " +
                                        std::to_string(row_slots) + " slots for " +
-                                       std::to_string(A->nnz) + " entries");
-  its_matrix P;  // new arrays; moved into A once complete
+                                       std::to_string(entries) + " entries");
+  PackOut P;
   hipError_t e = hipMalloc(&P.sp, size_t(ns + 1) * sizeof(int64_t));
-  if (e == hipSuccess && total > 0) e = hipMalloc(&P.scol, size_t(total) * sizeof(int32_t));
-  if (e == hipSuccess && total > 0) e = hipMalloc(&P.sval, size_t(total) * sizeof(double));
-  if (e == hipSuccess && total > 0 && A->val32) e = hipMalloc(&P.sval32, size_t(total) * sizeof(float));
-  if (e == hipSuccess && total > 0 && A->val16) e = hipMalloc(&P.sval16, size_t(total) * sizeof(__half));
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.col, size_t(total) * sizeof(int32_t));
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.val, size_t(total) * sizeof(double));
+  if (e == hipSuccess && total > 0 && lowp && A->val32) e = hipMalloc(&P.val32, size_t(total) * sizeof(float));
+  if (e == hipSuccess && total > 0 && lowp && A->val16) e = hipMalloc(&P.val16, size_t(total) * sizeof(__half));
   if (e == hipSuccess)
     e = hipMemcpyAsync(P.sp, hsp.data(), size_t(ns + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && total > 0) {
     const int gs = int(std::min<int64_t>((ns * kSlice + kBlock - 1) / kBlock, 65536));
-    const int32_t ni = int32_t(n);
-    hipLaunchKernelGGL(k_sell_scatter<double>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
-                       A->val, (const int64_t *)P.sp, P.scol, P.sval);
-    if (A->val32)
-      hipLaunchKernelGGL(k_sell_scatter<float>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
-                         A->val32, (const int64_t *)P.sp, (int32_t *)nullptr, P.sval32);
-    if (A->val16)
-      hipLaunchKernelGGL(k_sell_scatter<__half>, dim3(gs), dim3(kBlock), 0, s, ni, A->rp, A->col,
-                         A->val16, (const int64_t *)P.sp, (int32_t *)nullptr, P.sval16);
+    const int32_t ci = int32_t(count);
+    hipLaunchKernelGGL(k_sell_scatter<double>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
+                       A->val, (const int64_t *)P.sp, P.col, P.val);
+    if (P.val32)
+      hipLaunchKernelGGL(k_sell_scatter<float>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
+                         A->val32, (const int64_t *)P.sp, (int32_t *)nullptr, P.val32);
+    if (P.val16)
+      hipLaunchKernelGGL(k_sell_scatter<__half>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
+                         A->val16, (const int64_t *)P.sp, (int32_t *)nullptr, P.val16);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    free_packed(&P);
+    P.release();
     return fail(ITS_E_HIP, std::string("packing: ") + hipGetErrorString(e));
   }
-  A->sp = P.sp;
-  A->scol = P.scol;
-  A->sval = P.sval;
-  A->sval32 = P.sval32;
-  A->sval16 = P.sval16;
-  A->sell_entries = total;
-  P.sp = nullptr;
-  P.scol = nullptr;
-  P.sval = nullptr;
-  P.sval32 = nullptr;
-  P.sval16 = nullptr;
+  P.slots = total;
+  out = P;
   return ITS_OK;
+}
+
+// Packs each colour's rows for the Gauss-Seidel half-sweeps; a colour that
+// would exceed the fill bound leaves every colour on the CSR arrays.
+static its_status pack_colors(its_matrix *A, hipStream_t s) {
+  free_color_packs(A);
+  if (A->ncolors == 0 || A->pack_fill == 0.0) return ITS_OK;
+  std::vector<its_matrix::ColorPack> packs;
+  for (int32_t c = 0; c < A->ncolors; ++c) {
+    const int32_t beg = A->color_off[size_t(c)], cnt = A->color_off[size_t(c) + 1] - beg;
+    PackOut P;
+    its_status st = pack_rows(A, A->color_rows + beg, cnt, A->pack_fill, false, s, P);
+    if (st != ITS_OK) {
+      for (auto &q : packs) {
+        if (q.sp) (void)hipFree(q.sp);
+        if (q.col) (void)hipFree(q.col);
+        if (q.val) (void)hipFree(q.val);
+      }
+      if (st == ITS_E_UNSUPPORTED) {
+        g_err.clear();
+        return ITS_OK;
+      }
+      return st;
+    }
+    its_matrix::ColorPack cp;
+    cp.sp = P.sp;
+    cp.col = P.col;
+    cp.val = P.val;
+    packs.push_back(cp);
+  }
+  A->cpack = packs;
+  return ITS_OK;
+}
+
+its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (!(max_fill >= 1.0) || !std::isfinite(max_fill))
+    return fail(ITS_E_INVALID, "max_fill must be finite and >= 1");
+  free_packed(A);
+  if (A->n == 0) return ITS_OK;
+  hipStream_t s = S(stream);
+  PackOut P;
+  its_status st = pack_rows(A, nullptr, A->n, max_fill, true, s, P);
+  if (st != ITS_OK) return st;
+  A->sp = P.sp;
+  A->scol = P.col;
+  A->sval = P.val;
+  A->sval32 = P.val32;
+  A->sval16 = P.val16;
+  A->sell_entries = P.slots;
+  A->pack_fill = max_fill;
+  return pack_colors(A, s);
 }
 
 int64_t its_csr_packed_slots(const its_matrix *A) { return A && A->sp ? A->sell_entries : 0; }
@@ -1050,7 +1143,7 @@ its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolo
   A->color_rows = d;
   A->color_off = off;
   A->ncolors = ncolors;
-  return ITS_OK;
+  return pack_colors(A, s);
 }
 
 its_status its_spmv(const its_matrix *A, const double *x, double *y, void *stream) {

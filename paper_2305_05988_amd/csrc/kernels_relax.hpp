@@ -3,6 +3,7 @@
 
 #include "common.hpp"
 #include "csr.hpp"
+#include "sell.hpp"
 #include "stencil.hpp"
 
 namespace its {
@@ -77,6 +78,29 @@ __global__ void __launch_bounds__(kBlock) k_gs_rows_csr(CsrOp<double, double> A,
     double full, off, diag;
     A.relax(i, [&](int32_t j) { return x[j]; }, full, off, diag);
     x[i] = (b[i] - off) / diag;
+  });
+}
+
+// The same half-sweep over a colour's rows in their own packed layout (row p
+// of the layout is rows[p]), so the entries stream coalesced.
+__global__ void __launch_bounds__(kBlock) k_gs_rows_packed(SellOp<double, double> A,
+                                                           const int32_t *__restrict__ rows,
+                                                           const double *__restrict__ b, double *x,
+                                                           const State *st) {
+  __shared__ SellOp<double, double>::Smem sm;
+  if (st->flag != kRunning) return;
+  auto xj = [&](int32_t j) { return x[j]; };
+  for_tiles(A.n, [&](int32_t r0, int32_t r1) {
+    const int32_t p = r0 + int32_t(threadIdx.x);
+    const int32_t i = p < r1 ? rows[p] : -1;
+    double off = 0.0, diag = 0.0;
+    A.tile_entries(r0, r1, sm, xj, [&](int32_t j, double av, double v) {
+      if (j != i)
+        off = fma(av, v, off);
+      else
+        diag = av;
+    });
+    if (p < r1) x[i] = (b[i] - off) / diag;
   });
 }
 

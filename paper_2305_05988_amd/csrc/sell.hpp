@@ -131,17 +131,23 @@ struct SellOp {
 
 // ------------------------------------------------------------------ packing
 
+// The packed layout covers `count` rows: row p of the layout is matrix row
+// rows[p], or p itself when rows is null (a colour's rows for the
+// Gauss-Seidel half-sweeps, or the whole matrix in order).
+//
 // Width of each slice; a row whose pointers are out of order or outside
 // [0, nnz] is counted in *bad and given width 0.
-__global__ void __launch_bounds__(kBlock) k_sell_width(int32_t n, int32_t nnz,
+__global__ void __launch_bounds__(kBlock) k_sell_width(int32_t count, int32_t nnz,
                                                        const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ rows,
                                                        int32_t *__restrict__ width, uint32_t *bad) {
-  const int64_t ns = (int64_t(n) + kSlice - 1) / kSlice;
+  const int64_t ns = (int64_t(count) + kSlice - 1) / kSlice;
   for (int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x; s < ns;
        s += int64_t(gridDim.x) * kBlock) {
     int32_t w = 0;
-    const int32_t i1 = int32_t(min(int64_t(n), (s + 1) * kSlice));
-    for (int32_t i = int32_t(s * kSlice); i < i1; ++i) {
+    const int32_t p1 = int32_t(min(int64_t(count), (s + 1) * kSlice));
+    for (int32_t p = int32_t(s * kSlice); p < p1; ++p) {
+      const int32_t i = rows ? rows[p] : p;
       const int32_t b = rp[i], e = rp[i + 1];
       if (b < 0 || e < b || e > nnz) {
         atomicAdd(bad, 1u);
@@ -157,21 +163,23 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int32_t n, int32_t nnz,
 // row's end, including the rows of the last slice beyond n) into the
 // sliced layout.  col_out may be null to pack values only.
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t n, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t count, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ rows,
                                                          const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const int64_t *__restrict__ sp,
                                                          int32_t *__restrict__ col_out,
                                                          V *__restrict__ val_out) {
-  const int64_t rows = (int64_t(n) + kSlice - 1) / kSlice * kSlice;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < rows;
-       i += int64_t(gridDim.x) * kBlock) {
-    const int64_t s = i / kSlice;
-    const int32_t l = int32_t(i % kSlice);
+  const int64_t slots = (int64_t(count) + kSlice - 1) / kSlice * kSlice;
+  for (int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x; p < slots;
+       p += int64_t(gridDim.x) * kBlock) {
+    const int64_t s = p / kSlice;
+    const int32_t l = int32_t(p % kSlice);
     const int64_t base = sp[s];
     const int32_t w = int32_t((sp[s + 1] - base) / kSlice);
     int32_t b = 0, len = 0;
-    if (i < n) {
+    if (p < count) {
+      const int32_t i = rows ? rows[p] : int32_t(p);
       b = rp[i];
       len = min(rp[i + 1] - b, w);
       if (len < 0) len = 0;

@@ -317,7 +317,7 @@ def test_jacobi_converges_upwind():
 # ------------------------------------------------------------ Gauss-Seidel
 
 @pytest.mark.parametrize("k", [1, 2, 9])
-@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "sten27", "csr7p"])
+@pytest.mark.parametrize("kind", ["csr7", "sten7", "csr27", "sten27", "csr7p", "csr27p"])
 def test_sgs_fixed_k_bit_exact(kind, k):
     g = (11, 7, 6)
     Acsr, A = _matrix(kind, g)
@@ -345,6 +345,25 @@ def test_sgs_converged_32cube_redblack():
     S = its().StencilMatrix(*g, inputs.POISSON7)
     x2, info2 = its().solve(S, dev(b), method="sgs", rtol=1e-8, max_iter=5000)
     assert info2.iters == rr.iters and np.array_equal(host(x2), ref)
+
+
+@pytest.mark.parametrize("pack_first", [False, True])
+def test_sgs_packed_colours_in_either_order(pack_first):
+    g = (13, 9, 7)
+    Acsr = inputs.poisson7_csr(*g)
+    col = inputs.redblack_colors(*g)
+    A = its().CSRMatrix.from_numpy(*Acsr)
+    if pack_first:
+        A.pack(max_fill=2.0)
+        A.set_colors(col, 2)
+    else:
+        A.set_colors(col, 2)
+        A.pack(max_fill=2.0)
+    xs, b = _system(Acsr)
+    ref, rr = oracle.sgs(Acsr, col, 2, b, rtol=1e-8, max_iter=2000)
+    x, info = its().solve(A, dev(b), method="sgs", rtol=1e-8, max_iter=2000)
+    assert rr.status == oracle.OK and info.iters == rr.iters
+    assert np.array_equal(host(x), ref)
 
 
 def test_sgs_rejects_bad_colouring():
