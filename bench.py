@@ -289,14 +289,16 @@ def small32(its, inputs, N=32):
     out = {}
     for method, cap in (("cg", 5000), ("bicgstab", 5000), ("cgnb", 5000), ("jacobi", 2000),
                         ("sgs", 5000)):
-        its.solve(A, b, method=method, rtol=1e-8, max_iter=cap)
-        ts = []
-        for _ in range(5):
-            t, (x, info) = timed(lambda: its.solve(A, b, method=method, rtol=1e-8, max_iter=cap))
-            ts.append(t)
-        t = statistics.median(ts)
-        out[method] = {"iters": info.iters, "status": info.status, "s": t,
-                       "iters_per_s": info.iters / t}
+        for graph in (False, True):
+            its.solve(A, b, method=method, rtol=1e-8, max_iter=cap, graph=graph)
+            ts = []
+            for _ in range(5):
+                t, (x, info) = timed(lambda: its.solve(A, b, method=method, rtol=1e-8,
+                                                       max_iter=cap, graph=graph))
+                ts.append(t)
+            t = statistics.median(ts)
+            out[method + ("_graph" if graph else "")] = {
+                "iters": info.iters, "status": info.status, "s": t, "iters_per_s": info.iters / t}
     log(f"32^3: {json.dumps(out)}")
     return out
 

@@ -71,6 +71,13 @@ typedef struct {
                            reflected; variable-coefficient diffusion is
                            symmetric); ITS_E_UNSUPPORTED for CSR.  Used for
                            the adjoint solve of a differentiable solve */
+  int32_t graph;        /* 1: run the iteration loop as a HIP graph of
+                           check_every iterations (captured on the first solve
+                           with a given matrix, method, vectors and workspace,
+                           on a stream the handle owns, then replayed; results
+                           are identical to launch-by-launch).  Not with
+                           profile.  0 (default): launch kernel by kernel */
+  int32_t pad;
 } its_options;
 
 #define ITS_MAX_KERNEL_CLASSES 8

@@ -34,7 +34,8 @@ class Options(C.Structure):
                 ("max_iter", C.c_int64), ("restart_tol", C.c_double),
                 ("check_every", C.c_int32), ("inner_dtype", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int64),
-                ("profile", C.c_int32), ("transpose", C.c_int32)]
+                ("profile", C.c_int32), ("transpose", C.c_int32),
+                ("graph", C.c_int32), ("pad", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -217,7 +217,7 @@ class SolveInfo:
 
 def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mode="cosine",
             inner_dtype="f64", inner_rtol=1e-4, max_outer=30, check_every=0, profile=False,
-            transpose=False):
+            transpose=False, graph=False):
     o = L.Options()
     L.lib().its_default_options(C.byref(o))
     o.method = _METHODS[method]
@@ -231,6 +231,7 @@ def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mo
     o.check_every = check_every
     o.profile = int(profile)
     o.transpose = int(bool(transpose))
+    o.graph = int(bool(graph))
     return o
 
 

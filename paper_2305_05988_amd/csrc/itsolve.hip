@@ -52,7 +52,20 @@ struct its_matrix {
     double *val = nullptr;
   };
   std::vector<ColorPack> cpack;
+  // the iteration loop captured as a HIP graph, cached for one argument set
+  struct GraphCache {
+    hipStream_t s = nullptr;  // own stream: the caller's may be the legacy stream
+    hipEvent_t ev = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+  } graph;
 };
+
+static void drop_graph(its_matrix *A) {
+  if (A->graph.exec) (void)hipGraphExecDestroy(A->graph.exec);
+  A->graph.exec = nullptr;
+  A->graph.key.clear();
+}
 
 static void free_color_packs(its_matrix *A) {
   for (auto &c : A->cpack) {
@@ -63,7 +76,9 @@ static void free_color_packs(its_matrix *A) {
   A->cpack.clear();
 }
 
+static void drop_graph(its_matrix *A);
 static void free_packed(its_matrix *A) {
+  drop_graph(A);
   if (A->sp) (void)hipFree(A->sp);
   if (A->scol) (void)hipFree(A->scol);
   if (A->sval) (void)hipFree(A->sval);
@@ -153,6 +168,8 @@ struct Prof {
 struct Run {
   hipStream_t s;
   Prof prof;
+  its_matrix::GraphCache *gc = nullptr;  // null: launch each iteration eagerly
+  std::vector<uint64_t> key;             // what the captured launches depend on
   template <class K, class... Args>
   hipError_t launch(int cls, K kernel, int grid, Args... args) {
     prof.begin(cls, s);
@@ -326,8 +343,72 @@ int batch_size(const its_options *o, int64_t n) {
 
 // Runs iterations j = j0, j0+1, ... until the device flag leaves kRunning or
 // max_iter iterations were launched; `step(j)` launches iteration j.
+// Graph form of the loop: iterations 0..m-1 (or 1..m with the first run
+// eagerly, for a step whose first iteration differs) are captured once on
+// the handle's stream and replayed, with one poll of the State per replay.
+// m is even so that steps alternating buffers by the parity of j line up.
+// The limits live in the State, so the same graph serves every right-hand
+// side; the key holds every value the captured launches bake in.
 template <class Step>
-its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, int m, Step &&step) {
+its_status iterate_graph(Run &run, const State *dev, State *host, int64_t max_iter, int m,
+                         bool eager_first, Step &&step) {
+  its_matrix::GraphCache &G = *run.gc;
+  if (m & 1) ++m;
+  if (!G.s) {
+    HIP_TRY(hipStreamCreateWithFlags(&G.s, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&G.ev, hipEventDisableTiming));
+  }
+  int64_t j = 0;
+  if (eager_first) {
+    its_status st = step(0);
+    if (st != ITS_OK) return st;
+    j = 1;
+  }
+  std::vector<uint64_t> key = run.key;
+  key.push_back(uint64_t(m));
+  key.push_back(uint64_t(eager_first));
+  // order the graph after the work already on the caller's stream
+  HIP_TRY(hipEventRecord(G.ev, run.s));
+  HIP_TRY(hipStreamWaitEvent(G.s, G.ev, 0));
+  if (!G.exec || G.key != key) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    G.key.clear();
+    const hipStream_t saved = run.s;
+    run.s = G.s;
+    HIP_TRY(hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal));
+    its_status st = ITS_OK;
+    for (int t = 0; t < m && st == ITS_OK; ++t) st = step(j + t);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(G.s, &g);
+    run.s = saved;
+    if (st != ITS_OK) {
+      if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(ITS_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      G.exec = nullptr;
+      return fail(ITS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    G.key = key;
+  }
+  for (;;) {
+    HIP_TRY(hipGraphLaunch(G.exec, G.s));
+    j += m;
+    HIP_TRY(hipMemcpyAsync(host, dev, sizeof(State), hipMemcpyDeviceToHost, G.s));
+    HIP_TRY(hipStreamSynchronize(G.s));
+    if (host->flag != kRunning) return ITS_OK;
+    if (j >= max_iter + m) return fail(ITS_E_HIP, "device state still running after max_iter");
+  }
+}
+
+template <class Step>
+its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, int m, Step &&step,
+                   bool eager_first = false) {
+  if (run.gc && run.prof.every == 0) return iterate_graph(run, dev, host, max_iter, m, eager_first, step);
   int64_t j = 0;
   for (;;) {
     const int64_t todo = std::min<int64_t>(m, max_iter - j);
@@ -409,7 +490,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
@@ -417,7 +498,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
         LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), GA, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
         LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, rp, (const double *)q, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinCg2{w.st, thr2, o->max_iter}));
+        FINISH(run, 1, w.R, G, (FinCg2{w.st}));
         return ITS_OK;
       });
     });
@@ -456,7 +537,7 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
@@ -466,7 +547,7 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
         LAUNCH(run, 0, k_cgnb_x<decltype(op)>, GA, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCgnbX{w.st}));
         LAUNCH(run, 1, k_cgnb_y, G, n, x, ra, p, (const double *)wv, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinCgnbY{w.st, thr2, o->max_iter}));
+        FINISH(run, 1, w.R, G, (FinCgnbY{w.st}));
         return ITS_OK;
       });
     });
@@ -532,14 +613,14 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     const double ithr2 = threshold2(o->inner_rtol, rho_i);
     const int64_t budget = o->max_iter - inner_total;
     if (!(rho_i <= ithr2)) {
-      LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i);
+      LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i, ithr2, budget);
       s = with_op32(A, dt, [&](auto op) -> its_status {
         const int GA = op.grid();
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
           LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
           LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
-          FINISH(run, 1, w.R, G, (FinCg2{w.st2, ithr2, budget}));
+          FINISH(run, 1, w.R, G, (FinCg2{w.st2}));
           return ITS_OK;
         });
       });
@@ -582,7 +663,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
   if (flag == kRunning) {
     LAUNCH(run, kClassOther, k_bicg_init, G, n, (const double *)r, rs, w.R, std::sqrt(rr));
     FINISH(run, 1, w.R, G, (FinBicgInit{w.st}));
@@ -597,7 +678,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
         LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double *)r, (const double *)V[c], t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
         LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, (const State *)w.st, w.R);
-        FINISH(run, 2, w.R, G, (FinBicgC{w.st, thr2, o->max_iter, rt2, paper}));
+        FINISH(run, 2, w.R, G, (FinBicgC{w.st, rt2, paper}));
         return ITS_OK;
       });
     });
@@ -634,14 +715,14 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
     return ITS_OK;
   }
   const double thr2 = threshold2(o->rtol, bb);
-  LAUNCH(run, kClassOther, k_begin, 1, w.st, (int32_t)kRunning, 0.0);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, (int32_t)kRunning, 0.0, thr2, (int64_t)o->max_iter);
   // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
   s = with_op64(A, [&](auto op) -> its_status {
     const int GA = op.grid();
     return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
       LAUNCH(run, 0, k_jacobi<decltype(op)>, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
-      FINISH(run, 1, w.R, GA, (FinJacobi{w.st, thr2, o->max_iter}));
+      FINISH(run, 1, w.R, GA, (FinJacobi{w.st}));
       return ITS_OK;
     });
   });
@@ -679,7 +760,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   if (rr <= thr2) flag = kConverged;
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
-  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr);
+  LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
   // Colour order of iteration j: forward 0..nc-1 then backward nc-1..0.  The
   // backward sweep's first colour repeats the forward sweep's last one on
   // unchanged inputs, and the next forward sweep's colour 0 repeats this
@@ -719,9 +800,9 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
           if (e != ITS_OK) return e;
         }
         LAUNCH(run, 1, k_gs_check<decltype(op)>, GA, op, b, (const double *)x, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, GA, (FinGs{w.st, thr2, o->max_iter}));
+        FINISH(run, 1, w.R, GA, (FinGs{w.st}));
         return ITS_OK;
-      });
+      }, /*eager_first=*/true);
     });
     if (s != ITS_OK) return s;
   } else {
@@ -767,6 +848,7 @@ bool options_ok(const its_options *o, std::string &why) {
   if (o->max_outer < 0) { why = "max_outer must be >= 0"; return false; }
   if (o->profile < 0) { why = "profile must be >= 0"; return false; }
   if (o->transpose != 0 && o->transpose != 1) { why = "transpose must be 0 or 1"; return false; }
+  if (o->graph != 0 && o->graph != 1) { why = "graph must be 0 or 1"; return false; }
   return true;
 }
 
@@ -790,6 +872,7 @@ void its_default_options(its_options *o) {
   o->max_outer = 30;
   o->profile = 0;
   o->transpose = 0;
+  o->graph = 0;
 }
 
 const char *its_status_string(int32_t st) {
@@ -873,6 +956,9 @@ its_status its_matrix_destroy(its_matrix *A) {
   if (A->color_rows) (void)hipFree(A->color_rows);
   if (A->host_state) (void)hipHostFree(A->host_state);
   free_packed(A);
+  drop_graph(A);
+  if (A->graph.ev) (void)hipEventDestroy(A->graph.ev);
+  if (A->graph.s) (void)hipStreamDestroy(A->graph.s);
   delete A;
   return ITS_OK;
 }
@@ -937,6 +1023,7 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
 
 its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  drop_graph(A);
   if (A->sp) return fail(ITS_E_INVALID, "set low-precision values before its_csr_pack");
   if (!val_lo && A->nnz > 0) return fail(ITS_E_INVALID, "null values");
   if (reinterpret_cast<uintptr_t>(val_lo) % 16)
@@ -1049,6 +1136,7 @@ static its_status pack_rows(const its_matrix *A, const int32_t *rows, int64_t co
 // Packs each colour's rows for the Gauss-Seidel half-sweeps; a colour that
 // would exceed the fill bound leaves every colour on the CSR arrays.
 static its_status pack_colors(its_matrix *A, hipStream_t s) {
+  drop_graph(A);
   free_color_packs(A);
   if (A->ncolors == 0 || A->pack_fill == 0.0) return ITS_OK;
   std::vector<its_matrix::ColorPack> packs;
@@ -1243,6 +1331,27 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
   run.s = S(stream);
   run.prof.every = o->profile;
   run.prof.res = res;
+  // the iteration loops run as a cached HIP graph (eagerly when profiling);
+  // the key lists what the captured launches depend on
+  its_matrix *owner = const_cast<its_matrix *>(Ac);
+  run.gc = o->graph == 1 ? &owner->graph : nullptr;
+  {
+    uint64_t rt;
+    std::memcpy(&rt, &o->restart_tol, sizeof(rt));
+    run.key = {uint64_t(o->method), uint64_t(o->inner_dtype), uint64_t(o->restart_mode), rt,
+               uint64_t(o->transpose), uint64_t(reinterpret_cast<uintptr_t>(Ac)),
+               uint64_t(reinterpret_cast<uintptr_t>(A->sp)), uint64_t(A->cpack.size()),
+               uint64_t(reinterpret_cast<uintptr_t>(A->color_rows)), uint64_t(A->kind),
+               uint64_t(reinterpret_cast<uintptr_t>(b)), uint64_t(reinterpret_cast<uintptr_t>(x)),
+               uint64_t(reinterpret_cast<uintptr_t>(workspace)), uint64_t(A->n),
+               uint64_t(reinterpret_cast<uintptr_t>(A->val32)),
+               uint64_t(reinterpret_cast<uintptr_t>(A->val16))};
+    for (int q = 0; q < 27; ++q) {
+      uint64_t c;
+      std::memcpy(&c, &A->coef[q], sizeof(c));
+      run.key.push_back(c);
+    }
+  }
   const WS w = carve(workspace, L, A->n);
   if (o->method == ITS_JACOBI || o->method == ITS_SGS) {
     its_status s = check_diag(run, A, w);

@@ -27,8 +27,13 @@ struct FinDot {
   __device__ void operator()(DD (&v)[1]) const { st->dot[out] = dd_round(v[0]); }
 };
 
-__global__ void k_begin(State *st, int32_t flag, double rho) {
+// Start of an iteration loop; the stopping threshold and the iteration cap
+// live in the State so that a captured graph of iterations serves any
+// right-hand side.
+__global__ void k_begin(State *st, int32_t flag, double rho, double thr2, int64_t max_iter) {
   if (threadIdx.x != 0) return;
+  st->thr2 = thr2;
+  st->max_iter = max_iter;
   st->flag = flag;
   st->k = 0;
   st->restart = 0;

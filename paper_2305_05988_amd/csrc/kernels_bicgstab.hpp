@@ -183,8 +183,6 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
 // restart decided in its last iteration).
 struct FinBicgC {
   State *st;
-  double thr2;
-  int64_t max_iter;
   double restart_tol2;
   int32_t paper_mode;
   __device__ bool active() const { return st->flag == kRunning; }
@@ -196,7 +194,7 @@ struct FinBicgC {
     st->k = k;
     st->rho = beta;
     if (half) {
-      st->flag = (beta <= thr2) ? kConverged : kBreakdown;
+      st->flag = (beta <= st->thr2) ? kConverged : kBreakdown;
       return;
     }
     const bool want = paper_mode ? (__builtin_fabs(an) < restart_tol2)
@@ -209,11 +207,11 @@ struct FinBicgC {
       st->beta = an / (st->alpha_d * om);
       st->alpha_n = an;
     }
-    if (beta <= thr2)
+    if (beta <= st->thr2)
       st->flag = kConverged;
     else if (!finite(beta))
       st->flag = kBreakdown;
-    else if (k >= max_iter)
+    else if (k >= st->max_iter)
       st->flag = kMaxIter;
   }
 };

@@ -93,8 +93,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
 // rho' = r.r, one more iteration, beta = rho'/rho, convergence test.
 struct FinCg2 {
   State *st;
-  double thr2;
-  int64_t max_iter;
   __device__ bool active() const { return st->flag == kRunning; }
   __device__ void operator()(DD (&v)[1]) const {
     const double rho_new = dd_round(v[0]);
@@ -102,11 +100,11 @@ struct FinCg2 {
     st->k = k;
     st->beta = rho_new / st->rho;
     st->rho = rho_new;
-    if (rho_new <= thr2)
+    if (rho_new <= st->thr2)
       st->flag = kConverged;
     else if (!finite(rho_new))
       st->flag = kBreakdown;
-    else if (k >= max_iter)
+    else if (k >= st->max_iter)
       st->flag = kMaxIter;
   }
 };

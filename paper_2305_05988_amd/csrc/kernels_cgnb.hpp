@@ -132,19 +132,17 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_y(int32_t n, double *__restrict
 // x_j just formed); alpha_j for the next pass X.
 struct FinCgnbY {
   State *st;
-  double thr2;
-  int64_t max_iter;
   __device__ bool active() const { return st->flag == kRunning; }
   __device__ void operator()(DD (&v)[1]) const {
     const double ad = dd_round(v[0]), an = st->alpha_n;
     const int64_t k = st->k + 1;
     st->k = k;
     st->rho = an;
-    if (an <= thr2)
+    if (an <= st->thr2)
       st->flag = kConverged;
     else if (!finite(an))
       st->flag = kBreakdown;
-    else if (k >= max_iter)
+    else if (k >= st->max_iter)
       st->flag = kMaxIter;
     else if (ad == 0.0 || !finite(ad))
       st->flag = kBreakdown;

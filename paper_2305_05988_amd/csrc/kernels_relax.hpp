@@ -45,18 +45,16 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restric
 // new iterate.
 struct FinJacobi {
   State *st;
-  double thr2;
-  int64_t max_iter;
   __device__ bool active() const { return st->flag == kRunning; }
   __device__ void operator()(DD (&v)[1]) const {
     const double rr = dd_round(v[0]);
     const int64_t k = st->k;
     st->rho = rr;
-    if (rr <= thr2)
+    if (rr <= st->thr2)
       st->flag = kConverged;
     else if (!finite(rr))
       st->flag = kBreakdown;
-    else if (k >= max_iter)
+    else if (k >= st->max_iter)
       st->flag = kMaxIter;
     else
       st->k = k + 1;
@@ -148,19 +146,17 @@ __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restr
 // Residual of x_{k+1} after a symmetric iteration, and the test.
 struct FinGs {
   State *st;
-  double thr2;
-  int64_t max_iter;
   __device__ bool active() const { return st->flag == kRunning; }
   __device__ void operator()(DD (&v)[1]) const {
     const double rr = dd_round(v[0]);
     const int64_t k = st->k + 1;
     st->k = k;
     st->rho = rr;
-    if (rr <= thr2)
+    if (rr <= st->thr2)
       st->flag = kConverged;
     else if (!finite(rr))
       st->flag = kBreakdown;
-    else if (k >= max_iter)
+    else if (k >= st->max_iter)
       st->flag = kMaxIter;
   }
 };

@@ -40,7 +40,7 @@ def test_default_options(lib):
     lib.its_default_options(C.byref(o))
     assert o.method == L.ITS_CG and o.rtol == 1e-8 and o.max_iter == 10000
     assert o.restart_tol == 1e-5 and o.restart_mode == L.ITS_RESTART_COSINE
-    assert o.inner_dtype == L.ITS_F64 and o.profile == 0
+    assert o.inner_dtype == L.ITS_F64 and o.profile == 0 and o.graph == 0 and o.transpose == 0
 
 
 def test_status_strings(lib):

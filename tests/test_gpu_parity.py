@@ -536,3 +536,29 @@ def test_full_size_poisson256_packed_cg():
     assert info.iters == rr.iters == 2
     assert ulps(xg, ref) == 0
     assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
+
+
+# ------------------------------------------------------------ graph replays
+
+@pytest.mark.parametrize("method,kind,extra", [
+    ("cg", "csr7p", {}), ("cg", "sten7", {}), ("cgnb", "csr7p", {}), ("bicgstab", "csrcdp", {}),
+    ("jacobi", "csrcdp", {}), ("sgs", "csr7p", {}), ("sgs", "sten27", {}),
+    ("cg", "csr27p", {"inner_dtype": "f16", "inner_rtol": 1e-3}), ("bicgstab", "stencd", {"transpose": True})])
+def test_graph_replays_match_eager_launches(method, kind, extra):
+    """The iteration loop runs as a captured HIP graph (graph=True) or launch
+    by launch; both must give the same bits, over repeated solves and with a
+    new right-hand side through the cached graph."""
+    g = (13, 11, 9)
+    Acsr, A = _matrix(kind, g)
+    if method == "sgs" and kind.startswith("csr"):
+        A.set_colors(inputs.redblack_colors(*g), 2)
+    cap = 60 if method in ("jacobi", "sgs") else 400
+    for seed in (1, 2):
+        xs, b = _system(Acsr, seed=seed)
+        bt = dev(b)
+        ref, ri = its().solve(A, bt, method=method, rtol=1e-9, max_iter=cap, **extra)
+        for _ in range(2):
+            x, info = its().solve(A, bt, method=method, rtol=1e-9, max_iter=cap, check_every=4,
+                                  graph=True, **extra)
+            assert info.iters == ri.iters and info.status == ri.status
+            assert np.array_equal(host(x), host(ref))
