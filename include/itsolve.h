@@ -273,7 +273,7 @@ typedef struct {
   int32_t status;          /* ITS_OK if every (system, rhs) converged, else
                               ITS_BREAKDOWN if any broke down, else
                               ITS_NOT_CONVERGED */
-  int32_t tiles_per_item;  /* the autotuner's choice */
+  int32_t tiles_per_item;  /* the autotuner's choice, or the fixed one */
   int32_t graph_iters;     /* m */
   int32_t pad;
   int64_t max_iters;       /* largest iteration count over (system, rhs) */
@@ -294,6 +294,12 @@ its_status its_batch_destroy(its_batch *B);
 int64_t its_batch_cells(const its_batch *B);
 /* Bytes of device workspace its_batch_solve needs (256-byte aligned). */
 size_t its_batch_workspace_size(const its_batch *B);
+/* Fixes the number of tiles one work item covers (tiles_per_item >= 1), in
+   place of the autotuner's choice; 0 hands the choice back to the autotuner
+   at the next solve.  Results do not depend on it (the reductions round
+   their exact sums).  ITS_E_INVALID for a null handle or a negative value.
+   Synchronises the handle's stream. */
+its_status its_batch_set_tiles(its_batch *B, int32_t tiles_per_item);
 /* Solves every (system, rhs) with FP64 CG (opts: method ITS_CG, inner_dtype
    ITS_F64, rtol, max_iter per (system, rhs), check_every = m).  b, x: device,
    cells * nrhs float64 (x: x0 in, solution out); b = 0 for a (system, rhs)

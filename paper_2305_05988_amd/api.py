@@ -364,6 +364,11 @@ class Batch:
         n = np.prod(self.dims.astype(np.int64), axis=1)
         return np.concatenate([[0], np.cumsum(n)[:-1]])
 
+    def set_tiles_per_item(self, tiles):
+        """Fix the work-item length (tiles of 256/nrhs cells); 0 returns the
+        choice to the autotuner."""
+        L.check(L.lib().its_batch_set_tiles(self._h, int(tiles)), "its_batch_set_tiles")
+
     def solve(self, b, x0=None, rtol=1e-8, max_iter=10000, check_every=0):
         n = self.cells * self.nrhs
         b = _vec(b, n, "b")

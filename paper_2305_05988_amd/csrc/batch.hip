@@ -40,7 +40,7 @@ struct its_batch {
   // graph of m iterations, cached for one set of arguments
   hipGraphExec_t gexec = nullptr;
   std::vector<uintptr_t> gkey;
-  int32_t *h_count = nullptr;  // pinned
+  int32_t *h_count = nullptr;  // pinned: items still running
 };
 
 namespace {
@@ -79,9 +79,9 @@ int pass_grid(int nitems) {
   return std::max(g, 1);
 }
 
-// Workspace: [BatchCg S R][sys_run S][run_count][partials cap R 2 DD][pairs][q]
+// Workspace: [BatchCg S R][sys_run S][sys_base S][nact][act cap][partials cap R 2 DD][pairs][q]
 struct BatchWs {
-  size_t st, run, count, part, pairs, q, total;
+  size_t st, run, base, nact, act, part, pairs, q, total;
 };
 
 BatchWs batch_layout(const its_batch *B) {
@@ -90,8 +90,10 @@ BatchWs batch_layout(const its_batch *B) {
   const size_t S = size_t(B->nsys), R = size_t(B->nrhs);
   L.st = 0;
   L.run = up(S * R * sizeof(BatchCg));
-  L.count = L.run + up(S * sizeof(int32_t));
-  L.part = L.count + 256;
+  L.base = L.run + up(S * sizeof(int32_t));
+  L.nact = L.base + up(S * sizeof(int32_t));
+  L.act = L.nact + 256;
+  L.part = L.act + up(size_t(B->item_cap) * sizeof(BatchAct));
   L.pairs = L.part + up(size_t(B->item_cap) * R * 2 * sizeof(DD));
   L.q = L.pairs + up(size_t(B->ncell) * R * 16);
   L.total = L.q + up(size_t(B->ncell) * R * 8);
@@ -110,9 +112,36 @@ BatchView view_of(const its_batch *B, char *ws, const BatchWs &L) {
   V.coef = B->coef;
   V.st = reinterpret_cast<BatchCg *>(ws + L.st);
   V.sys_run = reinterpret_cast<int32_t *>(ws + L.run);
-  V.run_count = reinterpret_cast<int32_t *>(ws + L.count);
+  V.sys_base = reinterpret_cast<int32_t *>(ws + L.base);
+  V.nact = reinterpret_cast<int32_t *>(ws + L.nact);
+  V.act = reinterpret_cast<BatchAct *>(ws + L.act);
   V.part = reinterpret_cast<DD *>(ws + L.part);
   return V;
+}
+
+// The running systems' items, gathered for the two passes.
+void launch_compact(hipStream_t s, const BatchView &V) {
+  hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(kBlock), 0, s, V);
+  hipLaunchKernelGGL(k_batch_compact, dim3(V.nsys), dim3(kBlock), 0, s, V);
+}
+
+// The two passes, instantiated per right-hand-side count.
+void launch_pass1(int G, hipStream_t s, const BatchView &V, const double2_t *pairs, double *q) {
+  switch (V.nrhs) {
+    case 1: hipLaunchKernelGGL(k_batch_pass1<1>, dim3(G), dim3(kBlock), 0, s, V, pairs, q); break;
+    case 2: hipLaunchKernelGGL(k_batch_pass1<2>, dim3(G), dim3(kBlock), 0, s, V, pairs, q); break;
+    case 4: hipLaunchKernelGGL(k_batch_pass1<4>, dim3(G), dim3(kBlock), 0, s, V, pairs, q); break;
+    default: hipLaunchKernelGGL(k_batch_pass1<8>, dim3(G), dim3(kBlock), 0, s, V, pairs, q); break;
+  }
+}
+
+void launch_pass2(int G, hipStream_t s, const BatchView &V, double *x, double2_t *pairs, const double *q) {
+  switch (V.nrhs) {
+    case 1: hipLaunchKernelGGL(k_batch_pass2<1>, dim3(G), dim3(kBlock), 0, s, V, x, pairs, q); break;
+    case 2: hipLaunchKernelGGL(k_batch_pass2<2>, dim3(G), dim3(kBlock), 0, s, V, x, pairs, q); break;
+    case 4: hipLaunchKernelGGL(k_batch_pass2<4>, dim3(G), dim3(kBlock), 0, s, V, x, pairs, q); break;
+    default: hipLaunchKernelGGL(k_batch_pass2<8>, dim3(G), dim3(kBlock), 0, s, V, x, pairs, q); break;
+  }
 }
 
 __global__ void k_batch_fill_run(int32_t *run, int n) {
@@ -141,9 +170,10 @@ its_status autotune(its_batch *B, char *ws, const BatchWs &L) {
     auto *q = reinterpret_cast<double *>(ws + L.q);
     hipLaunchKernelGGL(k_batch_fill_run, dim3(std::max(1, (B->nsys + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        V.sys_run, B->nsys);
-    hipLaunchKernelGGL(k_batch_pass1, dim3(G), dim3(kBlock), 0, s, V, pairs, q);  // warm-up
+    launch_compact(s, V);
+    launch_pass1(G, s, V, pairs, q);  // warm-up
     (void)hipEventRecord(a, s);
-    for (int rep = 0; rep < 3; ++rep) hipLaunchKernelGGL(k_batch_pass1, dim3(G), dim3(kBlock), 0, s, V, pairs, q);
+    for (int rep = 0; rep < 3; ++rep) launch_pass1(G, s, V, pairs, q);
     (void)hipEventRecord(b, s);
     if (hipEventSynchronize(b) != hipSuccess) {
       rs = its_fail(ITS_E_HIP, "autotune timing");
@@ -199,6 +229,8 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     sy.nx = nx;
     sy.ny = ny;
     sy.nz = nz;
+    sy.dx = make_divisor(uint32_t(nx));
+    sy.dy = make_divisor(uint32_t(ny));
     const int64_t n = int64_t(nx) * ny * nz;
     sy.tiles = int32_t((n + cpt - 1) / cpt);
     max_tiles_items += sy.tiles;
@@ -273,6 +305,17 @@ int64_t its_batch_cells(const its_batch *B) { return B ? B->ncell : -1; }
 
 size_t its_batch_workspace_size(const its_batch *B) { return B ? batch_layout(B).total : 0; }
 
+its_status its_batch_set_tiles(its_batch *B, int32_t tiles_per_item) {
+  if (!B) return its_fail(ITS_E_INVALID, "null batch");
+  if (tiles_per_item < 0) return its_fail(ITS_E_INVALID, "tiles_per_item must be >= 0");
+  drop_graph(B);
+  B->tune_ms = 0.0;
+  B->chunk = tiles_per_item;
+  if (tiles_per_item == 0) return ITS_OK;
+  build_items(B, tiles_per_item);
+  return upload_schedule(B, B->stream);
+}
+
 its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, double *x,
                            void *workspace, size_t ws_bytes, void *stream, its_batch_result *res,
                            int64_t *iters, int32_t *status) {
@@ -317,14 +360,15 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
   BHIP(hipMemcpyAsync(V.st, hst.data(), hst.size() * sizeof(BatchCg), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_batch_begin, dim3(S), dim3(kBlock), 0, s, V, (int64_t)o->max_iter);
   hipLaunchKernelGGL(k_batch_zero, dim3(G), dim3(kBlock), 0, s, V, x);
-  hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(kBlock), 0, s, V);
+  launch_compact(s, V);
   BHIP(hipGetLastError());
-  BHIP(hipMemcpyAsync(B->h_count, V.run_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(B->h_count, V.nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
   const int m = o->check_every > 0 ? o->check_every : 16;
   int64_t replays = 0;
   if (*B->h_count > 0) {
-    // one graph: m iterations of the four kernels, then the running count
+    // one graph: m iterations (the four CG kernels, then the gathering of
+    // the running systems' items, whose count the host polls)
     const std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(b), reinterpret_cast<uintptr_t>(x),
                                         reinterpret_cast<uintptr_t>(ws), uintptr_t(m),
                                         uintptr_t(o->max_iter), uintptr_t(B->chunk)};
@@ -333,12 +377,12 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
       hipGraph_t g = nullptr;
       BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < m; ++it) {
-        hipLaunchKernelGGL(k_batch_pass1, dim3(G), dim3(kBlock), 0, s, V, (const double2_t *)pairs, q);
+        launch_pass1(G, s, V, pairs, q);
         hipLaunchKernelGGL(k_batch_fin1, dim3(S), dim3(kBlock), 0, s, V);
-        hipLaunchKernelGGL(k_batch_pass2, dim3(G), dim3(kBlock), 0, s, V, x, pairs, (const double *)q);
+        launch_pass2(G, s, V, x, pairs, q);
         hipLaunchKernelGGL(k_batch_fin2, dim3(S), dim3(kBlock), 0, s, V, (int64_t)o->max_iter);
+        launch_compact(s, V);
       }
-      hipLaunchKernelGGL(k_batch_count, dim3(1), dim3(kBlock), 0, s, V);
       hipError_t ce = hipStreamEndCapture(s, &g);
       if (ce != hipSuccess) return its_fail(ITS_E_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
       ce = hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0);
@@ -354,7 +398,7 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
     for (;;) {
       BHIP(hipGraphLaunch(B->gexec, s));
       ++replays;
-      BHIP(hipMemcpyAsync(B->h_count, V.run_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      BHIP(hipMemcpyAsync(B->h_count, V.nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       BHIP(hipStreamSynchronize(s));
       if (*B->h_count == 0) break;
       if (replays > max_replays) return its_fail(ITS_E_HIP, "batched solve still running after max_iter");

@@ -15,19 +15,52 @@ namespace its {
 // 0 outside the grid), coef[o * ncell + g], and reused by all R right-hand
 // sides.  Work items are runs of 256/R-cell tiles inside one system; each
 // item leaves one double-double partial per right-hand side, and one block
-// per system finishes the reductions in a fixed order.
+// per system finishes the reductions in a fixed order.  After every
+// iteration the items of the systems still running are gathered, with all
+// a block needs to start loading, into a dense list that the two CG passes
+// walk, so stopped systems cost nothing and the work stays spread evenly.
 constexpr int kBatchMaxRhs = 8;
+
+// Division of an unsigned 32-bit value by a fixed divisor d >= 1 as a
+// multiply-high and shifts (Granlund and Montgomery, 1994: m = floor(2^32
+// (2^l - d) / d) + 1 with l = ceil(log2 d)), exact for every 32-bit value.
+struct Divisor {
+  uint32_t m, s1, s2;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    const uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
+inline Divisor make_divisor(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  Divisor v;
+  v.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+  v.s1 = l < 1 ? l : 1;
+  v.s2 = l > 1 ? l - 1 : 0;
+  return v;
+}
 
 struct BatchSys {
   int64_t off;           // first global cell
   int32_t nx, ny, nz;
   int32_t tiles;         // ceil(n / cells per tile)
   int32_t item0, item1;  // its work items
+  Divisor dx, dy;        // by nx and by ny
+  int32_t pad;
 };
 
 struct BatchItem {
   int32_t sys, t0, t1;   // tiles [t0, t1) of system sys
   int32_t pad;
+};
+
+// An item of a running system, as the CG passes read it.
+struct BatchAct {
+  BatchSys sy;
+  int32_t w;             // the item's index (its partial slot)
+  int32_t sys, t0, t1;
 };
 
 // CG scalars of one (system, right-hand side).
@@ -47,7 +80,9 @@ struct BatchView {
   const double *coef;
   BatchCg *st;
   int32_t *sys_run;  // per system: 1 while any of its right-hand sides runs
-  int32_t *run_count;  // systems still running (written by k_batch_count)
+  int32_t *sys_base; // per system: its first slot in act (running systems)
+  int32_t *nact;     // items of the running systems
+  BatchAct *act;     // those items, in system and item order
   DD *part;          // [item][rhs][2]
 };
 
@@ -272,33 +307,145 @@ __global__ void __launch_bounds__(kBlock) k_batch_zero(BatchView V, double *__re
 }
 
 // CG pass 1: p = r + beta p formed on the fly, q = A p, partial p.q.
+//
+// Rows of one work item are consecutive cells, so the x and y neighbours of
+// a tile of C = 256/R cells all lie in the cell window [L - nx, L + C + nx).
+// The block keeps that window, as formed p values, in an LDS ring of S cells
+// and slides it by one tile per step: each step loads only the C cells that
+// enter the window (one coalesced load per thread, two steps ahead) and
+// gathers just the two z neighbours (one step ahead), so a step's loads are
+// in flight while earlier tiles are computed.  The 7 coefficients of a cell
+// are read once by the R lanes that share it (lane r takes coefficients r,
+// r + R, ...) and passed between those lanes.  Systems with nx too large
+// for the ring (2 C + 2 nx > S) take the gather path.  Both paths run the
+// same chain.
+constexpr int kRingVals = 2048;  // doubles: 16 KB of LDS
+
+template <int R>
 __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const double2_t *__restrict__ rp,
                                                         double *__restrict__ q) {
-  const int R = V.nrhs, cl = threadIdx.x / R, r = threadIdx.x % R;
-  const Sched sc = my_tiles(V.nitems);
+  constexpr int C = kBlock / R, S = kRingVals / R, kL = (7 + R - 1) / R;
+  __shared__ double ring[kRingVals];
+  const int cl = threadIdx.x / R, r = threadIdx.x % R;
+  const Sched sc = my_tiles(*V.nact);
   for (int64_t w = sc.begin; w < sc.end; w += sc.stride) {
-    const BatchItem it = V.items[w];
-    if (!V.sys_run[it.sys]) continue;  // block-uniform
-    const BatchSys sy = V.sys[it.sys];
+    const BatchAct it = V.act[w];
+    const BatchSys &sy = it.sy;
     const BatchCg &c = V.st[it.sys * R + r];
     const bool first = c.k == 0;
     const double beta = c.beta;
-    const int64_t n = int64_t(sy.nx) * sy.ny * sy.nz;
+    auto value = [&](const double2_t &v) { return first ? v.x : fma(beta, v.y, v.x); };
+    const int32_t nx = sy.nx;
+    const int64_t n = int64_t(nx) * sy.ny * sy.nz;
     Dot2 a;
-    for (int32_t t = it.t0; t < it.t1; ++t) {
-      const int64_t lc = int64_t(t) * V.cells + cl;
-      if (lc < n) {
-        double pi;
-        const double acc = batch_row(V, sy, lc, r, [&](int64_t e) { return rp[e]; },
-                                     [&](const double2_t &v) { return first ? v.x : fma(beta, v.y, v.x); },
-                                     pi);
-        st_nt(q + (sy.off + lc) * R + r, acc);
-        a.add(pi, acc);
+    if (2 * C + 2 * nx <= S && n * R < (int64_t(1) << 31)) {
+      // cell and element indices of this system fit 32 bits here
+      const int32_t nn = int32_t(n), nxy = nx * sy.ny;
+      const double2_t *rs = rp + sy.off * R + r;  // (cell 0, rhs r) of this system
+      const double *cf = V.coef + sy.off;          // coefficient o of cell c: cf[o ncell + c]
+      auto slot = [&](int32_t cell) -> double & { return ring[(cell & (S - 1)) * R + r]; };
+      // what a tile gathers besides the window: its z neighbours and this
+      // lane's share of the coefficients
+      struct Ahead {
+        int32_t lc, ix, iy, iz;
+        double2_t zm, zp;
+        double cv[kL];
+      };
+      auto gather = [&](int32_t t, Ahead &g) {
+        const int32_t lc = t * C + cl;
+        g.lc = lc < nn ? lc : 0;
+        const int32_t tq = int32_t(sy.dx.div(uint32_t(g.lc)));
+        g.ix = g.lc - tq * nx;
+        g.iz = int32_t(sy.dy.div(uint32_t(tq)));
+        g.iy = tq - g.iz * sy.ny;
+        g.zm = rs[(g.iz > 0 ? g.lc - nxy : g.lc) * R];
+        g.zp = rs[(g.iz < sy.nz - 1 ? g.lc + nxy : g.lc) * R];
+#pragma unroll
+        for (int j = 0; j < kL; ++j) {
+          const int o = r + j * R;
+          g.cv[j] = cf[int64_t(o < 7 ? o : 6) * V.ncell + g.lc];
+        }
+        g.lc = lc;
+      };
+      Ahead cur;
+      gather(it.t0, cur);
+      // the window of the first tile, loaded in rounds of C cells, four
+      // rounds in flight at a time
+      const int32_t A = it.t0 * C;
+      const int32_t lo = A - nx > 0 ? A - nx : 0;
+      const int32_t hi = A + C + nx < nn ? A + C + nx : nn;
+      // the cells entering the window of the second tile
+      int32_t pc = A + C + nx + cl;
+      bool pf = it.t0 + 1 < it.t1 && pc < nn;
+      double2_t pv = rs[(pf ? pc : 0) * R];
+      for (int32_t u0 = lo; u0 < hi; u0 += 4 * C) {  // block-uniform
+        double2_t pre[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t cc = u0 + u * C + cl;
+          pre[u] = rs[(cc < hi ? cc : lo) * R];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t cc = u0 + u * C + cl;
+          if (cc < hi) slot(cc) = value(pre[u]);
+        }
+      }
+      __syncthreads();
+      for (int32_t t = it.t0; t < it.t1; ++t) {
+        // loads for later steps: the cells entering the window of tile
+        // t + 2, the gathers of tile t + 1
+        const int32_t pc2 = pc + C;
+        const bool pf2 = t + 2 < it.t1 && pc2 < nn;
+        const double2_t pv2 = rs[(pf2 ? pc2 : 0) * R];
+        const bool more = t + 1 < it.t1;  // block-uniform
+        Ahead nxt;
+        if (more) gather(t + 1, nxt);
+        double co[7];
+        if constexpr (R == 1) {
+#pragma unroll
+          for (int o = 0; o < 7; ++o) co[o] = cur.cv[o];
+        } else {
+          const int base = int(threadIdx.x & 63) & ~(R - 1);
+#pragma unroll
+          for (int o = 0; o < 7; ++o) co[o] = __shfl(cur.cv[o / R], base | (o % R), 64);
+        }
+        const bool valid = cur.lc < nn;
+        const int32_t lcs = valid ? cur.lc : 0;
+        const bool in[7] = {cur.iz > 0,      cur.iy > 0,          cur.ix > 0,         true,
+                            cur.ix < nx - 1, cur.iy < sy.ny - 1, cur.iz < sy.nz - 1};
+        const double xv[7] = {value(cur.zm),  slot(lcs - nx), slot(lcs - 1), slot(lcs),
+                              slot(lcs + 1),  slot(lcs + nx), value(cur.zp)};
+        double acc = 0.0;
+#pragma unroll
+        for (int o = 0; o < 7; ++o)
+          if (in[o]) acc = fma(co[o], xv[o], acc);
+        if (valid) {
+          st_nt(q + (sy.off + cur.lc) * R + r, acc);
+          a.add(xv[3], acc);
+        }
+        // the window of tile t + 1 is complete after this write
+        if (pf) slot(pc) = value(pv);
+        __syncthreads();
+        pc = pc2;
+        pf = pf2;
+        pv = pv2;
+        if (more) cur = nxt;
+      }
+    } else {
+      for (int32_t t = it.t0; t < it.t1; ++t) {
+        const int64_t lc = int64_t(t) * C + cl;
+        if (lc < n) {
+          double pi;
+          const double acc = batch_row(V, sy, lc, r, [&](int64_t e) { return rp[e]; }, value, pi);
+          st_nt(q + (sy.off + lc) * R + r, acc);
+          a.add(pi, acc);
+        }
       }
     }
     DD v[2] = {a.get(), DD{0.0, 0.0}};
     batch_block_reduce<2>(v, R);
-    if (int(threadIdx.x) < R) V.part[(int64_t(w) * R + threadIdx.x) * 2] = v[0];
+    if (int(threadIdx.x) < R) V.part[(int64_t(it.w) * R + threadIdx.x) * 2] = v[0];
   }
 }
 
@@ -320,39 +467,60 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin1(BatchView V) {
 }
 
 // CG pass 2: p = r + beta p stored, x += alpha p, r -= alpha q, partial r.r.
+// Pass 2 has no neighbours, so the P items of a system take its tiles
+// round-robin (item j: tiles j, j + P, j + 2P, ...): the blocks that run
+// side by side then stream through neighbouring tiles.  Four tiles per
+// step, their loads issued together (index clamped to the system's first
+// cell where a tile runs past the system).
+template <int R>
 __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__restrict__ x,
                                                         double2_t *__restrict__ rp,
                                                         const double *__restrict__ q) {
-  const int R = V.nrhs, cl = threadIdx.x / R, r = threadIdx.x % R;
-  const Sched sc = my_tiles(V.nitems);
+  constexpr int C = kBlock / R, U = 4;
+  const int cl = threadIdx.x / R, r = threadIdx.x % R;
+  const Sched sc = my_tiles(*V.nact);
   for (int64_t w = sc.begin; w < sc.end; w += sc.stride) {
-    const BatchItem it = V.items[w];
-    if (!V.sys_run[it.sys]) continue;
-    const BatchSys sy = V.sys[it.sys];
+    const BatchAct it = V.act[w];
+    const BatchSys &sy = it.sy;
     const BatchCg &c = V.st[it.sys * R + r];
     const bool run = c.flag == kRunning;
     const bool first = c.k == 0;
     const double beta = c.beta, alpha = c.alpha;
     const int64_t n = int64_t(sy.nx) * sy.ny * sy.nz;
+    const int64_t e0 = sy.off * R + r;
+    const int32_t P = sy.item1 - sy.item0, j = it.w - sy.item0;
     Dot2 a;
-    for (int32_t t = it.t0; t < it.t1; ++t) {
-      const int64_t lc = int64_t(t) * V.cells + cl;
-      if (lc < n && run) {
-        const int64_t e = (sy.off + lc) * R + r;
-        const double2_t v = ld_nt(rp + e);
-        const double pi = first ? v.x : fma(beta, v.y, v.x);
-        st_nt(x + e, fma(alpha, pi, ld_nt(x + e)));
-        const double ri = fma(-alpha, ld_nt(q + e), v.x);
+    for (int32_t t = j; t < sy.tiles; t += U * P) {
+      bool ok[U];
+      int64_t e[U];
+      double2_t v[U];
+      double xo[U], qo[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t tt = t + u * P;
+        const int64_t lc = int64_t(tt) * C + cl;
+        ok[u] = run && tt < sy.tiles && lc < n;
+        e[u] = e0 + (ok[u] ? lc : 0) * R;
+        v[u] = ld_nt(rp + e[u]);
+        xo[u] = ld_nt(x + e[u]);
+        qo[u] = ld_nt(q + e[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!ok[u]) continue;
+        const double pi = first ? v[u].x : fma(beta, v[u].y, v[u].x);
+        st_nt(x + e[u], fma(alpha, pi, xo[u]));
+        const double ri = fma(-alpha, qo[u], v[u].x);
         double2_t o;
         o.x = ri;
         o.y = pi;
-        st_nt(rp + e, o);
+        st_nt(rp + e[u], o);
         a.add(ri, ri);
       }
     }
     DD v[2] = {a.get(), DD{0.0, 0.0}};
     batch_block_reduce<2>(v, R);
-    if (int(threadIdx.x) < R) V.part[(int64_t(w) * R + threadIdx.x) * 2] = v[0];
+    if (int(threadIdx.x) < R) V.part[(int64_t(it.w) * R + threadIdx.x) * 2] = v[0];
   }
 }
 
@@ -387,16 +555,51 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin2(BatchView V, int64_t max_
   if (threadIdx.x == 0) V.sys_run[s] = any;
 }
 
-// Systems still running, for the host's poll.
-__global__ void __launch_bounds__(kBlock) k_batch_count(BatchView V) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
+// Items of the running systems: exclusive prefix over the systems (one
+// block; thread t takes a contiguous run of systems) and the total, which
+// the host also polls (0 once every system has stopped).
+__global__ void __launch_bounds__(kBlock) k_batch_scan(BatchView V) {
+  __shared__ int32_t part[kBlock];
+  const int t = threadIdx.x;
+  const int32_t lo = int32_t(int64_t(V.nsys) * t / kBlock), hi = int32_t(int64_t(V.nsys) * (t + 1) / kBlock);
+  int32_t sum = 0;
+  for (int32_t u = lo; u < hi; ++u)
+    if (V.sys_run[u]) sum += V.sys[u].item1 - V.sys[u].item0;
+  part[t] = sum;
   __syncthreads();
-  int mine = 0;
-  for (int s = threadIdx.x; s < V.nsys; s += kBlock) mine += V.sys_run[s];
-  atomicAdd(&cnt, mine);
+  if (t == 0) {
+    int32_t acc = 0;
+    for (int j = 0; j < kBlock; ++j) {
+      const int32_t v = part[j];
+      part[j] = acc;
+      acc += v;
+    }
+    *V.nact = acc;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) *V.run_count = cnt;
+  int32_t acc = part[t];
+  for (int32_t u = lo; u < hi; ++u) {
+    V.sys_base[u] = acc;
+    if (V.sys_run[u]) acc += V.sys[u].item1 - V.sys[u].item0;
+  }
+}
+
+// The records of the running systems' items (one block per system).
+__global__ void __launch_bounds__(kBlock) k_batch_compact(BatchView V) {
+  const int s = blockIdx.x;
+  if (!V.sys_run[s]) return;  // block-uniform
+  const BatchSys sy = V.sys[s];
+  const int32_t base = V.sys_base[s];
+  for (int32_t j = threadIdx.x; j < sy.item1 - sy.item0; j += kBlock) {
+    const BatchItem it = V.items[sy.item0 + j];
+    BatchAct a;
+    a.sy = sy;
+    a.w = sy.item0 + j;
+    a.sys = s;
+    a.t0 = it.t0;
+    a.t1 = it.t1;
+    V.act[base + j] = a;
+  }
 }
 
 }  // namespace its

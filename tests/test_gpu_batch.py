@@ -119,3 +119,48 @@ def test_batch_autotuner_reports_its_choice():
     assert info.tiles_per_item in (1, 2, 4, 8, 16, 32) and info.tune_ms > 0
     x, info2 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
     assert info2.tiles_per_item == info.tiles_per_item and info2.tune_ms == info.tune_ms
+
+
+def _explicit(dims, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    dims = np.array(dims, dtype=np.int32)
+    n = int(np.sum(np.prod(dims.astype(np.int64), axis=1)))
+    k = np.exp(rng.standard_normal(n))
+    b = rng.uniform(-1.0, 1.0, size=(n, nrhs))
+    return dims, k, b, its().Batch(dims, dev(k), nrhs)
+
+
+# The SpMV pass keeps a window of 256/R + 2 nx cells in LDS when it fits
+# (nx <= 768 / R); wider rows gather.  Systems at the limit, just past it,
+# a single cell, and rows shorter than a tile; items of 1, 3 and 16 tiles.
+@pytest.mark.parametrize("nrhs,dims", [
+    (8, [(96, 4, 3), (97, 3, 2), (5, 7, 3), (1, 1, 1)]),
+    (4, [(192, 2, 3), (193, 2, 2), (3, 9, 2)]),
+    (2, [(384, 1, 3), (385, 2, 1), (1, 1, 1)]),
+    (1, [(768, 2, 1), (769, 1, 2), (2, 3, 40)]),
+])
+@pytest.mark.parametrize("tiles", [1, 3, 16])
+def test_batch_window_and_gather_rows_bit_exact(nrhs, dims, tiles):
+    k = 5
+    dims, kc, b, B = _explicit(dims, nrhs, seed=19)
+    B.set_tiles_per_item(tiles)
+    x, info = B.solve(dev(b.ravel()), rtol=0.0, max_iter=k)
+    assert info.tiles_per_item == tiles and info.tune_ms == 0.0
+    ref = _oracle_each(dims, kc, b, lambda A, bb: oracle.cg(A, bb, rtol=0.0, max_iter=k)[0])
+    for s, part in enumerate(_split(host(x), dims, nrhs)):
+        for r in range(nrhs):
+            assert np.array_equal(part[:, r], ref[s][r]), (s, r)
+
+
+def test_batch_results_independent_of_item_length():
+    nrhs = 8
+    dims, kc, b, B = _batch(5, nrhs, lo=6, hi=30, seed=20)
+    bt = dev(b.ravel())
+    runs = []
+    for tiles in (1, 2, 7, 32, 0):
+        B.set_tiles_per_item(tiles)
+        x, info = B.solve(bt, rtol=1e-9, max_iter=3000)
+        assert info.status == "ok"
+        runs.append((host(x), info.iters.copy()))
+    for xr, it in runs[1:]:
+        assert np.array_equal(xr, runs[0][0]) and np.array_equal(it, runs[0][1])
