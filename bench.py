@@ -110,6 +110,8 @@ def main():
                     help="device layout of the CSR matrix (packed: its_csr_pack)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
+    ap.add_argument("--extra-only", choices=("batched", "small32", "differentiation"),
+                    help="profiling: run only this secondary workload and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
@@ -126,6 +128,10 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.extra_only:
+        fn = {"batched": batched, "small32": small32, "differentiation": differentiation}
+        print(json.dumps({args.extra_only: fn[args.extra_only](its, inputs)}), flush=True)
+        return
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
