@@ -338,6 +338,7 @@ def batched(its, inputs, nsys=512, nrhs=8):
     out = {"systems": nsys, "rhs": nrhs, "cells": int(n_s.sum()), "setup_s": setup,
            "status": info.status, "solve_s": dt, "first_solve_s": first.solve_ms / 1e3,
            "tune_ms": first.tune_ms, "tiles_per_item": info.tiles_per_item,
+           "planes_per_brick": info.planes_per_brick,
            "graph_iters": info.graph_iters, "replays": info.replays,
            "iters_max": int(it.max()), "iters_mean": float(it.mean()), "iters_min": int(it.min()),
            "solves_per_s": nsys * nrhs / dt,

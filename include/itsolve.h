@@ -259,7 +259,7 @@ const char *its_last_error(void); /* message of this thread's last error */
    (system, right-hand side) and advanced together.  The paper's experiments
    solve one large system per run; the batch is this library's analogue of
    choosing the task granularity (Section 3.2): an autotuner picks how many
-   tiles of a system one work item covers, by timing the SpMV pass on the
+   z planes one brick of the SpMV pass covers, by timing that pass on the
    first solve.  Each (system, rhs) follows exactly the arithmetic of the
    single-system CG (the same iterates, bit for bit) and stops on its own
    test; m = check_every iterations (default 16) are captured in one HIP
@@ -273,9 +273,10 @@ typedef struct {
   int32_t status;          /* ITS_OK if every (system, rhs) converged, else
                               ITS_BREAKDOWN if any broke down, else
                               ITS_NOT_CONVERGED */
-  int32_t tiles_per_item;  /* the autotuner's choice, or the fixed one */
+  int32_t tiles_per_item;  /* work-item length of the update passes */
   int32_t graph_iters;     /* m */
-  int32_t pad;
+  int32_t planes_per_brick; /* z planes per brick of the SpMV pass (the
+                               autotuner's choice, or the fixed one) */
   int64_t max_iters;       /* largest iteration count over (system, rhs) */
   int64_t replays;         /* graph launches */
   double tune_ms;          /* time of the autotuning (first solve) */
@@ -294,12 +295,13 @@ its_status its_batch_destroy(its_batch *B);
 int64_t its_batch_cells(const its_batch *B);
 /* Bytes of device workspace its_batch_solve needs (256-byte aligned). */
 size_t its_batch_workspace_size(const its_batch *B);
-/* Fixes the number of tiles one work item covers (tiles_per_item >= 1), in
-   place of the autotuner's choice; 0 hands the choice back to the autotuner
-   at the next solve.  Results do not depend on it (the reductions round
-   their exact sums).  ITS_E_INVALID for a null handle or a negative value.
-   Synchronises the handle's stream. */
-its_status its_batch_set_tiles(its_batch *B, int32_t tiles_per_item);
+/* Fixes the work schedule: tiles_per_item, the tiles of 256/nrhs cells one
+   work item of the update passes covers (0: the default, 16), and
+   planes_per_brick, the z planes one brick of the SpMV pass covers (0: the
+   autotuner chooses at the next solve).  Results do not depend on either
+   (the reductions round their exact sums).  ITS_E_INVALID for a null handle
+   or a negative value.  Synchronises the handle's stream. */
+its_status its_batch_set_schedule(its_batch *B, int32_t tiles_per_item, int32_t planes_per_brick);
 /* Solves every (system, rhs) with FP64 CG (opts: method ITS_CG, inner_dtype
    ITS_F64, rtol, max_iter per (system, rhs), check_every = m).  b, x: device,
    cells * nrhs float64 (x: x0 in, solution out); b = 0 for a (system, rhs)

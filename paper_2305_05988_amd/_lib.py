@@ -25,7 +25,7 @@ EXPORTS = (
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
     "its_csr_pack", "its_csr_packed_slots", "its_varcoef_create", "its_varcoef_grad",
     "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
-    "its_batch_solve", "its_batch_set_tiles",
+    "its_batch_solve", "its_batch_set_schedule",
 )
 
 
@@ -48,7 +48,7 @@ class Result(C.Structure):
 
 class BatchResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("tiles_per_item", C.c_int32),
-                ("graph_iters", C.c_int32), ("pad", C.c_int32), ("max_iters", C.c_int64),
+                ("graph_iters", C.c_int32), ("planes_per_brick", C.c_int32), ("max_iters", C.c_int64),
                 ("replays", C.c_int64), ("tune_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
@@ -78,7 +78,7 @@ def load(path: str = LIB_PATH):
         "its_batch_cells": (I64, [P]),
         "its_batch_workspace_size": (SZ, [P]),
         "its_batch_solve": (st, [P, P, P, P, P, SZ, P, P, P, P]),
-        "its_batch_set_tiles": (st, [P, I32]),
+        "its_batch_set_schedule": (st, [P, I32, I32]),
         "its_csr_packed_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),

@@ -328,6 +328,7 @@ class BatchInfo:
     iters: np.ndarray       # [nsys, nrhs]
     statuses: np.ndarray    # [nsys, nrhs] ITS_OK / ITS_NOT_CONVERGED / ITS_BREAKDOWN
     tiles_per_item: int
+    planes_per_brick: int
     graph_iters: int
     max_iters: int
     replays: int
@@ -364,10 +365,12 @@ class Batch:
         n = np.prod(self.dims.astype(np.int64), axis=1)
         return np.concatenate([[0], np.cumsum(n)[:-1]])
 
-    def set_tiles_per_item(self, tiles):
-        """Fix the work-item length (tiles of 256/nrhs cells); 0 returns the
-        choice to the autotuner."""
-        L.check(L.lib().its_batch_set_tiles(self._h, int(tiles)), "its_batch_set_tiles")
+    def set_schedule(self, tiles_per_item=0, planes_per_brick=0):
+        """Fix the work-item length of the update passes (tiles of 256/nrhs
+        cells; 0: the default) and the z planes per brick of the SpMV pass
+        (0: chosen by the autotuner at the next solve)."""
+        L.check(L.lib().its_batch_set_schedule(self._h, int(tiles_per_item), int(planes_per_brick)),
+                "its_batch_set_schedule")
 
     def solve(self, b, x0=None, rtol=1e-8, max_iter=10000, check_every=0):
         n = self.cells * self.nrhs
@@ -385,6 +388,6 @@ class Batch:
                                              iters.ctypes.data_as(C.c_void_p),
                                              stats.ctypes.data_as(C.c_void_p)), "its_batch_solve")
         info = BatchInfo(_STATUS.get(st, str(st)), iters.reshape(self.nsys, self.nrhs),
-                         stats.reshape(self.nsys, self.nrhs), r.tiles_per_item, r.graph_iters,
+                         stats.reshape(self.nsys, self.nrhs), r.tiles_per_item, r.planes_per_brick, r.graph_iters,
                          r.max_iters, r.replays, r.tune_ms, r.solve_ms)
         return x, info

@@ -28,11 +28,17 @@ struct its_batch {
   std::vector<BatchSys> sys;
   BatchSys *d_sys = nullptr;
   double *coef = nullptr;
-  // work-item schedule (chosen by the autotuner on the first solve)
+  // work items of the update passes (tiles per item, fixed) and bricks of
+  // the SpMV pass (planes per brick, chosen by the autotuner on the first
+  // solve unless fixed)
   int32_t chunk = 0;
   std::vector<BatchItem> items;
   BatchItem *d_items = nullptr;
   int32_t item_cap = 0;
+  int32_t zb = 0;
+  std::vector<BatchBrick> bricks;
+  BatchBrick *d_bricks = nullptr;
+  int32_t brick_cap = 0;
   double tune_ms = 0.0;
   // the solve's own stream (graphs cannot be captured on the legacy stream)
   hipStream_t stream = nullptr;
@@ -45,9 +51,52 @@ struct its_batch {
 
 namespace {
 
-constexpr int kTuneChunks[] = {1, 2, 4, 8, 16, 32};
+constexpr int kDefaultTiles = 16;
+constexpr int kTunePlanes[] = {4, 8, 16, 32, 64};
 
 int cells_per_tile(int R) { return kBlock / R; }
+
+void brick_shape(int R, int &tx, int &ty) {
+  switch (R) {
+    case 1: tx = BrickShape<1>::TX; ty = BrickShape<1>::TY; break;
+    case 2: tx = BrickShape<2>::TX; ty = BrickShape<2>::TY; break;
+    case 4: tx = BrickShape<4>::TX; ty = BrickShape<4>::TY; break;
+    default: tx = BrickShape<8>::TX; ty = BrickShape<8>::TY; break;
+  }
+}
+
+int64_t count_bricks(const its_batch *B, int zb) {
+  int tx, ty;
+  brick_shape(B->nrhs, tx, ty);
+  int64_t c = 0;
+  for (const BatchSys &sy : B->sys)
+    c += int64_t((sy.nx + tx - 1) / tx) * ((sy.ny + ty - 1) / ty) * ((sy.nz + zb - 1) / zb);
+  return c;
+}
+
+// Bricks of each system: x tiles fastest, then y tiles, then z runs of zb
+// planes, so neighbouring bricks of a plane are dealt side by side.
+void build_bricks(its_batch *B, int zb) {
+  int tx, ty;
+  brick_shape(B->nrhs, tx, ty);
+  B->bricks.clear();
+  for (int32_t s = 0; s < B->nsys; ++s) {
+    BatchSys &sy = B->sys[size_t(s)];
+    sy.brick0 = int32_t(B->bricks.size());
+    for (int32_t z0 = 0; z0 < sy.nz; z0 += zb)
+      for (int32_t y0 = 0; y0 < sy.ny; y0 += ty)
+        for (int32_t x0 = 0; x0 < sy.nx; x0 += tx) {
+          BatchBrick br{};
+          br.sys = s;
+          br.x0 = x0;
+          br.y0 = y0;
+          br.z0 = z0;
+          br.z1 = std::min(sy.nz, z0 + zb);
+          B->bricks.push_back(br);
+        }
+    sy.brick1 = int32_t(B->bricks.size());
+  }
+}
 
 void build_items(its_batch *B, int chunk) {
   B->items.clear();
@@ -68,6 +117,9 @@ void build_items(its_batch *B, int chunk) {
 its_status upload_schedule(its_batch *B, hipStream_t s) {
   BHIP(hipMemcpyAsync(B->d_items, B->items.data(), B->items.size() * sizeof(BatchItem),
                       hipMemcpyHostToDevice, s));
+  if (!B->bricks.empty())
+    BHIP(hipMemcpyAsync(B->d_bricks, B->bricks.data(), B->bricks.size() * sizeof(BatchBrick),
+                        hipMemcpyHostToDevice, s));
   BHIP(hipMemcpyAsync(B->d_sys, B->sys.data(), B->sys.size() * sizeof(BatchSys), hipMemcpyHostToDevice, s));
   BHIP(hipStreamSynchronize(s));
   return ITS_OK;
@@ -79,9 +131,10 @@ int pass_grid(int nitems) {
   return std::max(g, 1);
 }
 
-// Workspace: [BatchCg S R][sys_run S][sys_base S][nact][act cap][partials cap R 2 DD][pairs][q]
+// Workspace: [BatchCg S R][sys_run S][sys_base 2S][nact 2][act cap][act1 cap1]
+// [partials cap R 2 DD][brick partials cap1 R 2 DD][pairs][q]
 struct BatchWs {
-  size_t st, run, base, nact, act, part, pairs, q, total;
+  size_t st, run, base, nact, act, act1, part, part1, pairs, q, total;
 };
 
 BatchWs batch_layout(const its_batch *B) {
@@ -91,10 +144,12 @@ BatchWs batch_layout(const its_batch *B) {
   L.st = 0;
   L.run = up(S * R * sizeof(BatchCg));
   L.base = L.run + up(S * sizeof(int32_t));
-  L.nact = L.base + up(S * sizeof(int32_t));
+  L.nact = L.base + up(2 * S * sizeof(int32_t));
   L.act = L.nact + 256;
-  L.part = L.act + up(size_t(B->item_cap) * sizeof(BatchAct));
-  L.pairs = L.part + up(size_t(B->item_cap) * R * 2 * sizeof(DD));
+  L.act1 = L.act + up(size_t(B->item_cap) * sizeof(BatchAct));
+  L.part = L.act1 + up(size_t(B->brick_cap) * sizeof(BatchActB));
+  L.part1 = L.part + up(size_t(B->item_cap) * R * 2 * sizeof(DD));
+  L.pairs = L.part1 + up(size_t(B->brick_cap) * R * 2 * sizeof(DD));
   L.q = L.pairs + up(size_t(B->ncell) * R * 16);
   L.total = L.q + up(size_t(B->ncell) * R * 8);
   return L;
@@ -115,11 +170,14 @@ BatchView view_of(const its_batch *B, char *ws, const BatchWs &L) {
   V.sys_base = reinterpret_cast<int32_t *>(ws + L.base);
   V.nact = reinterpret_cast<int32_t *>(ws + L.nact);
   V.act = reinterpret_cast<BatchAct *>(ws + L.act);
+  V.act1 = reinterpret_cast<BatchActB *>(ws + L.act1);
+  V.bricks = B->d_bricks;
   V.part = reinterpret_cast<DD *>(ws + L.part);
+  V.part1 = reinterpret_cast<DD *>(ws + L.part1);
   return V;
 }
 
-// The running systems' items, gathered for the two passes.
+// The running systems' items and bricks, gathered for the two passes.
 void launch_compact(hipStream_t s, const BatchView &V) {
   hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(kBlock), 0, s, V);
   hipLaunchKernelGGL(k_batch_compact, dim3(V.nsys), dim3(kBlock), 0, s, V);
@@ -149,23 +207,23 @@ __global__ void k_batch_fill_run(int32_t *run, int n) {
 }
 
 // Autotuner: times the SpMV pass (the pass that dominates an iteration) for
-// each candidate work-item length and keeps the fastest.  The pass only
-// writes q and the partials, which the prologue and iterations overwrite.
+// each candidate brick length in z and keeps the fastest.  The pass only
+// writes q and the brick partials, which the iterations overwrite.
 its_status autotune(its_batch *B, char *ws, const BatchWs &L) {
   hipStream_t s = B->stream;
   double best = 1e300;
-  int best_chunk = kTuneChunks[0];
+  int best_zb = kTunePlanes[0];
   hipEvent_t a, b;
   BHIP(hipEventCreate(&a));
   BHIP(hipEventCreate(&b));
   const auto t0 = std::chrono::steady_clock::now();
   its_status rs = ITS_OK;
-  for (int chunk : kTuneChunks) {
-    build_items(B, chunk);
-    if (int32_t(B->items.size()) > B->item_cap) continue;
+  for (int zb : kTunePlanes) {
+    build_bricks(B, zb);
+    if (int64_t(B->bricks.size()) > B->brick_cap) continue;
     if ((rs = upload_schedule(B, s)) != ITS_OK) break;
     BatchView V = view_of(B, ws, L);
-    const int G = pass_grid(V.nitems);
+    const int G = pass_grid(int32_t(B->bricks.size()));
     auto *pairs = reinterpret_cast<const double2_t *>(ws + L.pairs);
     auto *q = reinterpret_cast<double *>(ws + L.q);
     hipLaunchKernelGGL(k_batch_fill_run, dim3(std::max(1, (B->nsys + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
@@ -183,14 +241,14 @@ its_status autotune(its_batch *B, char *ws, const BatchWs &L) {
     (void)hipEventElapsedTime(&ms, a, b);
     if (ms < best) {
       best = ms;
-      best_chunk = chunk;
+      best_zb = zb;
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rs != ITS_OK) return rs;
-  B->chunk = best_chunk;
-  build_items(B, best_chunk);
+  B->zb = best_zb;
+  build_bricks(B, best_zb);
   B->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return upload_schedule(B, s);
 }
@@ -229,8 +287,6 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     sy.nx = nx;
     sy.ny = ny;
     sy.nz = nz;
-    sy.dx = make_divisor(uint32_t(nx));
-    sy.dy = make_divisor(uint32_t(ny));
     const int64_t n = int64_t(nx) * ny * nz;
     sy.tiles = int32_t((n + cpt - 1) / cpt);
     max_tiles_items += sy.tiles;
@@ -243,6 +299,12 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     return its_fail(ITS_E_UNSUPPORTED, "batch too large");
   }
   B->item_cap = int32_t(std::min<int64_t>(max_tiles_items, int64_t(1) << 30));
+  const int64_t max_bricks = count_bricks(B, 1);
+  if (max_bricks >= (int64_t(1) << 30)) {
+    delete B;
+    return its_fail(ITS_E_UNSUPPORTED, "batch too large");
+  }
+  B->brick_cap = int32_t(max_bricks);
   its_status rs = ITS_OK;
   do {
     if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
@@ -258,11 +320,14 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     B->h_count = static_cast<int32_t *>(p);
     if (hipMalloc(&B->d_sys, sizeof(BatchSys) * size_t(nsys)) != hipSuccess ||
         hipMalloc(&B->d_items, sizeof(BatchItem) * size_t(B->item_cap)) != hipSuccess ||
+        hipMalloc(&B->d_bricks, sizeof(BatchBrick) * size_t(B->brick_cap)) != hipSuccess ||
         hipMalloc(&B->coef, sizeof(double) * 7 * size_t(off)) != hipSuccess) {
       rs = its_fail(ITS_E_HIP, "device allocation failed");
       break;
     }
-    build_items(B, 1);
+    B->chunk = kDefaultTiles;
+    build_items(B, B->chunk);
+    build_bricks(B, kTunePlanes[0]);  // replaced by the autotuner's choice
     // the coefficients are formed on the caller's stream, after k is ready
     hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(B->d_sys, B->sys.data(), sizeof(BatchSys) * size_t(nsys), hipMemcpyHostToDevice, cs) != hipSuccess) {
@@ -293,6 +358,7 @@ its_status its_batch_destroy(its_batch *B) {
   drop_graph(B);
   if (B->d_sys) (void)hipFree(B->d_sys);
   if (B->d_items) (void)hipFree(B->d_items);
+  if (B->d_bricks) (void)hipFree(B->d_bricks);
   if (B->coef) (void)hipFree(B->coef);
   if (B->h_count) (void)hipHostFree(B->h_count);
   if (B->ev) (void)hipEventDestroy(B->ev);
@@ -305,14 +371,18 @@ int64_t its_batch_cells(const its_batch *B) { return B ? B->ncell : -1; }
 
 size_t its_batch_workspace_size(const its_batch *B) { return B ? batch_layout(B).total : 0; }
 
-its_status its_batch_set_tiles(its_batch *B, int32_t tiles_per_item) {
+its_status its_batch_set_schedule(its_batch *B, int32_t tiles_per_item, int32_t planes_per_brick) {
   if (!B) return its_fail(ITS_E_INVALID, "null batch");
-  if (tiles_per_item < 0) return its_fail(ITS_E_INVALID, "tiles_per_item must be >= 0");
+  if (tiles_per_item < 0 || planes_per_brick < 0)
+    return its_fail(ITS_E_INVALID, "tiles_per_item and planes_per_brick must be >= 0");
   drop_graph(B);
+  B->chunk = tiles_per_item > 0 ? tiles_per_item : kDefaultTiles;
+  build_items(B, B->chunk);
+  B->zb = planes_per_brick;
   B->tune_ms = 0.0;
-  B->chunk = tiles_per_item;
-  if (tiles_per_item == 0) return ITS_OK;
-  build_items(B, tiles_per_item);
+  if (planes_per_brick > 0) build_bricks(B, planes_per_brick);
+  // the device copy of the systems carries both ranges; an autotuned brick
+  // list is uploaded by the tuner
   return upload_schedule(B, B->stream);
 }
 
@@ -335,12 +405,12 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
   // order the solve after the caller's work
   BHIP(hipEventRecord(B->ev, cs));
   BHIP(hipStreamWaitEvent(s, B->ev, 0));
-  if (B->chunk == 0) {
+  if (B->zb == 0) {
     its_status rs = autotune(B, ws, L);
     if (rs != ITS_OK) return rs;
   }
   BatchView V = view_of(B, ws, L);
-  const int G = pass_grid(V.nitems);
+  const int G = pass_grid(V.nitems), G1 = pass_grid(int32_t(B->bricks.size()));
   auto *pairs = reinterpret_cast<double2_t *>(ws + L.pairs);
   auto *q = reinterpret_cast<double *>(ws + L.q);
   const int S = B->nsys, R = B->nrhs;
@@ -371,13 +441,14 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
     // the running systems' items, whose count the host polls)
     const std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(b), reinterpret_cast<uintptr_t>(x),
                                         reinterpret_cast<uintptr_t>(ws), uintptr_t(m),
-                                        uintptr_t(o->max_iter), uintptr_t(B->chunk)};
+                                        uintptr_t(o->max_iter), uintptr_t(B->chunk),
+                                        uintptr_t(B->zb)};
     if (!B->gexec || B->gkey != key) {
       drop_graph(B);
       hipGraph_t g = nullptr;
       BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < m; ++it) {
-        launch_pass1(G, s, V, pairs, q);
+        launch_pass1(G1, s, V, pairs, q);
         hipLaunchKernelGGL(k_batch_fin1, dim3(S), dim3(kBlock), 0, s, V);
         launch_pass2(G, s, V, x, pairs, q);
         hipLaunchKernelGGL(k_batch_fin2, dim3(S), dim3(kBlock), 0, s, V, (int64_t)o->max_iter);
@@ -417,6 +488,7 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
   }
   res->status = worst;
   res->tiles_per_item = B->chunk;
+  res->planes_per_brick = B->zb;
   res->graph_iters = m;
   res->max_iters = kmax;
   res->replays = replays;

@@ -13,42 +13,35 @@ namespace its {
 // and every access is coalesced.  The operator is stored once per cell as
 // its 7 coefficients in chain order (z-1, y-1, x-1, diagonal, x+1, y+1, z+1;
 // 0 outside the grid), coef[o * ncell + g], and reused by all R right-hand
-// sides.  Work items are runs of 256/R-cell tiles inside one system; each
-// item leaves one double-double partial per right-hand side, and one block
-// per system finishes the reductions in a fixed order.  After every
-// iteration the items of the systems still running are gathered, with all
-// a block needs to start loading, into a dense list that the two CG passes
+// sides.  The SpMV pass works on bricks (an x-y tile of a system marched
+// through a run of z planes), the other passes on work items (runs of
+// 256/R-cell tiles inside one system); each brick or item leaves one
+// double-double partial per right-hand side, and one block per system
+// finishes the reductions in a fixed order.  After every iteration the
+// bricks and items of the systems still running are gathered, with all a
+// block needs to start loading, into dense lists that the two CG passes
 // walk, so stopped systems cost nothing and the work stays spread evenly.
 constexpr int kBatchMaxRhs = 8;
 
-// Division of an unsigned 32-bit value by a fixed divisor d >= 1 as a
-// multiply-high and shifts (Granlund and Montgomery, 1994: m = floor(2^32
-// (2^l - d) / d) + 1 with l = ceil(log2 d)), exact for every 32-bit value.
-struct Divisor {
-  uint32_t m, s1, s2;
-  __device__ __forceinline__ uint32_t div(uint32_t n) const {
-    const uint32_t t = __umulhi(m, n);
-    return (t + ((n - t) >> s1)) >> s2;
-  }
+struct BatchSys {
+  int64_t off;             // first global cell
+  int32_t nx, ny, nz;
+  int32_t tiles;           // ceil(n / cells per tile)
+  int32_t item0, item1;    // its work items
+  int32_t brick0, brick1;  // its bricks
 };
 
-inline Divisor make_divisor(uint32_t d) {
-  uint32_t l = 0;
-  while ((uint64_t(1) << l) < d) ++l;
-  Divisor v;
-  v.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
-  v.s1 = l < 1 ? l : 1;
-  v.s2 = l > 1 ? l - 1 : 0;
-  return v;
-}
+// Brick of the SpMV pass: cells [x0, x0 + TX) x [y0, y0 + TY) x [z0, z1) of
+// system sys (clipped to the grid), with TX x TY = 2 * 256/R cells.
+struct BatchBrick {
+  int32_t sys, x0, y0, z0, z1, pad;
+};
 
-struct BatchSys {
-  int64_t off;           // first global cell
-  int32_t nx, ny, nz;
-  int32_t tiles;         // ceil(n / cells per tile)
-  int32_t item0, item1;  // its work items
-  Divisor dx, dy;        // by nx and by ny
-  int32_t pad;
+// A brick of a running system, as the SpMV pass reads it.
+struct BatchActB {
+  int64_t off;
+  int32_t b;             // the brick's index (its partial slot)
+  int32_t sys, nx, ny, nz, x0, y0, z0, z1, pad;
 };
 
 struct BatchItem {
@@ -80,10 +73,13 @@ struct BatchView {
   const double *coef;
   BatchCg *st;
   int32_t *sys_run;  // per system: 1 while any of its right-hand sides runs
-  int32_t *sys_base; // per system: its first slot in act (running systems)
-  int32_t *nact;     // items of the running systems
+  int32_t *sys_base; // per system: its first slot in act / act1 (running systems)
+  int32_t *nact;     // [0] items, [1] bricks of the running systems
   BatchAct *act;     // those items, in system and item order
+  BatchActB *act1;   // those bricks, in system and brick order
+  const BatchBrick *bricks;
   DD *part;          // [item][rhs][2]
+  DD *part1;         // [brick][rhs][2]
 };
 
 __device__ __forceinline__ void batch_coords(const BatchSys &sy, int64_t lc, int32_t &ix,
@@ -231,19 +227,20 @@ __global__ void __launch_bounds__(kBlock) k_batch_residual(BatchView V, const do
   }
 }
 
-// Totals of dots 0..ND-1 over system s's items, per rhs, valid in threads
-// 0..R-1 (called by the whole block).  Thread t adds items item0 + t/R,
-// item0 + t/R + 256/R, ... of rhs t % R in that order, then the fixed
-// block reduction combines them.
+// Totals of dots 0..ND-1 over the partial slots [w0, w1) of one system, per
+// rhs, valid in threads 0..R-1 (called by the whole block).  Thread t adds
+// slots w0 + t/R, w0 + t/R + 256/R, ... of rhs t % R in that order, then
+// the fixed block reduction combines them.
 template <int ND>
-__device__ __forceinline__ void batch_sums(const BatchView &V, const BatchSys &sy, double (&out)[ND]) {
+__device__ __forceinline__ void batch_sums(const BatchView &V, const DD *part, int32_t w0, int32_t w1,
+                                           double (&out)[ND]) {
   const int R = V.nrhs, r = threadIdx.x % R, j0 = threadIdx.x / R, step = kBlock / R;
   DD v[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) v[d] = DD{0.0, 0.0};
-  for (int32_t w = sy.item0 + j0; w < sy.item1; w += step) {
+  for (int32_t w = w0 + j0; w < w1; w += step) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d) v[d] = dd_add(v[d], V.part[(int64_t(w) * R + r) * 2 + d]);
+    for (int d = 0; d < ND; ++d) v[d] = dd_add(v[d], part[(int64_t(w) * R + r) * 2 + d]);
   }
   batch_block_reduce<ND>(v, R);
 #pragma unroll
@@ -254,7 +251,8 @@ __device__ __forceinline__ void batch_sums(const BatchView &V, const BatchSys &s
 __global__ void __launch_bounds__(kBlock) k_batch_sums(BatchView V) {
   const int s = blockIdx.x;
   double t[2];
-  batch_sums<2>(V, V.sys[s], t);
+  const BatchSys sy = V.sys[s];
+  batch_sums<2>(V, V.part, sy.item0, sy.item1, t);
   if (int(threadIdx.x) < V.nrhs) {
     BatchCg &c = V.st[s * V.nrhs + threadIdx.x];
     c.rho = t[0];
@@ -308,144 +306,150 @@ __global__ void __launch_bounds__(kBlock) k_batch_zero(BatchView V, double *__re
 
 // CG pass 1: p = r + beta p formed on the fly, q = A p, partial p.q.
 //
-// Rows of one work item are consecutive cells, so the x and y neighbours of
-// a tile of C = 256/R cells all lie in the cell window [L - nx, L + C + nx).
-// The block keeps that window, as formed p values, in an LDS ring of S cells
-// and slides it by one tile per step: each step loads only the C cells that
-// enter the window (one coalesced load per thread, two steps ahead) and
-// gathers just the two z neighbours (one step ahead), so a step's loads are
-// in flight while earlier tiles are computed.  The 7 coefficients of a cell
-// are read once by the R lanes that share it (lane r takes coefficients r,
-// r + R, ...) and passed between those lanes.  Systems with nx too large
-// for the ring (2 C + 2 nx > S) take the gather path.  Both paths run the
-// same chain.
-constexpr int kRingVals = 2048;  // doubles: 16 KB of LDS
+// A block marches one brick through its z planes.  Each plane of the brick's
+// tile, with a one-cell halo in x and y, is loaded once with coalesced loads
+// (the R right-hand sides of a cell are adjacent), formed into p values and
+// kept in LDS; four plane slots rotate, so planes z-1, z, z+1 are read from
+// LDS while plane z+2 is in flight.  Every neighbour of a row then comes from
+// LDS, and each value is read from memory once per brick plus its halo.  The
+// 7 coefficients of a cell are read once by the R lanes that share it (lane
+// r takes coefficients r, r + R, ...), one plane ahead, and passed between
+// those lanes.  The chain is the single-system one.
+template <int R>
+struct BrickShape;
+template <>
+struct BrickShape<1> {
+  static constexpr int TX = 64, TY = 8;
+};
+template <>
+struct BrickShape<2> {
+  static constexpr int TX = 32, TY = 8;
+};
+template <>
+struct BrickShape<4> {
+  static constexpr int TX = 32, TY = 4;
+};
+template <>
+struct BrickShape<8> {
+  static constexpr int TX = 16, TY = 4;
+};
 
 template <int R>
 __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const double2_t *__restrict__ rp,
                                                         double *__restrict__ q) {
-  constexpr int C = kBlock / R, S = kRingVals / R, kL = (7 + R - 1) / R;
-  __shared__ double ring[kRingVals];
-  const int cl = threadIdx.x / R, r = threadIdx.x % R;
-  const Sched sc = my_tiles(*V.nact);
+  constexpr int TX = BrickShape<R>::TX, TY = BrickShape<R>::TY;
+  constexpr int C = kBlock / R;                   // cells per layer of the block
+  constexpr int CPT = TX * TY / C;                // cells per thread per plane
+  constexpr int HX = TX + 2, HS = HX * (TY + 2);  // halo tile
+  constexpr int NV = HS * R, NR = (NV + kBlock - 1) / kBlock;
+  constexpr int kL = (7 + R - 1) / R;
+  static_assert(CPT * C == TX * TY, "brick tile must fill whole layers");
+  __shared__ double slot[4][NV];  // value (halo cell h, rhs r) at h R + r
+  const int t = threadIdx.x, r = t % R, cl = t / R;
+  const Sched sc = my_tiles(V.nact[1]);
   for (int64_t w = sc.begin; w < sc.end; w += sc.stride) {
-    const BatchAct it = V.act[w];
-    const BatchSys &sy = it.sy;
-    const BatchCg &c = V.st[it.sys * R + r];
+    const BatchActB bk = V.act1[w];
+    const BatchCg &c = V.st[bk.sys * R + r];
     const bool first = c.k == 0;
     const double beta = c.beta;
     auto value = [&](const double2_t &v) { return first ? v.x : fma(beta, v.y, v.x); };
-    const int32_t nx = sy.nx;
-    const int64_t n = int64_t(nx) * sy.ny * sy.nz;
-    Dot2 a;
-    if (2 * C + 2 * nx <= S && n * R < (int64_t(1) << 31)) {
-      // cell and element indices of this system fit 32 bits here
-      const int32_t nn = int32_t(n), nxy = nx * sy.ny;
-      const double2_t *rs = rp + sy.off * R + r;  // (cell 0, rhs r) of this system
-      const double *cf = V.coef + sy.off;          // coefficient o of cell c: cf[o ncell + c]
-      auto slot = [&](int32_t cell) -> double & { return ring[(cell & (S - 1)) * R + r]; };
-      // what a tile gathers besides the window: its z neighbours and this
-      // lane's share of the coefficients
-      struct Ahead {
-        int32_t lc, ix, iy, iz;
-        double2_t zm, zp;
-        double cv[kL];
-      };
-      auto gather = [&](int32_t t, Ahead &g) {
-        const int32_t lc = t * C + cl;
-        g.lc = lc < nn ? lc : 0;
-        const int32_t tq = int32_t(sy.dx.div(uint32_t(g.lc)));
-        g.ix = g.lc - tq * nx;
-        g.iz = int32_t(sy.dy.div(uint32_t(tq)));
-        g.iy = tq - g.iz * sy.ny;
-        g.zm = rs[(g.iz > 0 ? g.lc - nxy : g.lc) * R];
-        g.zp = rs[(g.iz < sy.nz - 1 ? g.lc + nxy : g.lc) * R];
+    const int32_t nx = bk.nx, ny = bk.ny, nz = bk.nz;
+    const int64_t nxy = int64_t(nx) * ny;
+    const double2_t *rs = rp + bk.off * R + r;  // (cell 0, rhs r) of this system
+    const double *cf = V.coef + bk.off;          // coefficient o of cell c: cf[o ncell + c]
+    // loads are unconditional (halo cells outside the grid load cell 0,
+    // never consumed) so a plane's loads stay in flight together
+    double2_t hv[NR];
+    auto issue = [&](int32_t z) {
+#pragma unroll
+      for (int u = 0; u < NR; ++u) {
+        const int v = t + u * kBlock, h = v / R;
+        const int32_t gx = bk.x0 - 1 + h % HX, gy = bk.y0 - 1 + h / HX;
+        const bool in = v < NV && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        hv[u] = rs[(in ? gx + int64_t(nx) * gy + nxy * z : 0) * R];
+      }
+    };
+    auto put = [&](int32_t z) {
+      double *d = slot[z & 3];
+#pragma unroll
+      for (int u = 0; u < NR; ++u)
+        if (t + u * kBlock < NV) d[t + u * kBlock] = value(hv[u]);
+    };
+    // this thread's cells of the tile: k = cl + u C
+    auto cell_of = [&](int u, int32_t &gx, int32_t &gy) {
+      const int k = cl + u * C;
+      gx = bk.x0 + k % TX;
+      gy = bk.y0 + k / TX;
+    };
+    auto coefs = [&](int32_t z, double (&cv)[CPT][kL]) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        int32_t gx, gy;
+        cell_of(u, gx, gy);
+        const int64_t cell = gx < nx && gy < ny ? gx + int64_t(nx) * gy + nxy * z : 0;
 #pragma unroll
         for (int j = 0; j < kL; ++j) {
           const int o = r + j * R;
-          g.cv[j] = cf[int64_t(o < 7 ? o : 6) * V.ncell + g.lc];
-        }
-        g.lc = lc;
-      };
-      Ahead cur;
-      gather(it.t0, cur);
-      // the window of the first tile, loaded in rounds of C cells, four
-      // rounds in flight at a time
-      const int32_t A = it.t0 * C;
-      const int32_t lo = A - nx > 0 ? A - nx : 0;
-      const int32_t hi = A + C + nx < nn ? A + C + nx : nn;
-      // the cells entering the window of the second tile
-      int32_t pc = A + C + nx + cl;
-      bool pf = it.t0 + 1 < it.t1 && pc < nn;
-      double2_t pv = rs[(pf ? pc : 0) * R];
-      for (int32_t u0 = lo; u0 < hi; u0 += 4 * C) {  // block-uniform
-        double2_t pre[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t cc = u0 + u * C + cl;
-          pre[u] = rs[(cc < hi ? cc : lo) * R];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t cc = u0 + u * C + cl;
-          if (cc < hi) slot(cc) = value(pre[u]);
+          cv[u][j] = cf[int64_t(o < 7 ? o : 6) * V.ncell + cell];
         }
       }
-      __syncthreads();
-      for (int32_t t = it.t0; t < it.t1; ++t) {
-        // loads for later steps: the cells entering the window of tile
-        // t + 2, the gathers of tile t + 1
-        const int32_t pc2 = pc + C;
-        const bool pf2 = t + 2 < it.t1 && pc2 < nn;
-        const double2_t pv2 = rs[(pf2 ? pc2 : 0) * R];
-        const bool more = t + 1 < it.t1;  // block-uniform
-        Ahead nxt;
-        if (more) gather(t + 1, nxt);
+    };
+    Dot2 a;
+    for (int32_t z = max(bk.z0 - 1, 0); z <= min(bk.z0 + 1, nz - 1); ++z) {
+      issue(z);
+      put(z);
+    }
+    double cv[CPT][kL];
+    coefs(bk.z0, cv);
+    __syncthreads();
+    for (int32_t z = bk.z0; z < bk.z1; ++z) {
+      const int32_t zn = z + 2;
+      const bool pf = zn <= bk.z1 && zn < nz;  // block-uniform
+      if (pf) issue(zn);
+      const bool more = z + 1 < bk.z1;         // block-uniform
+      double cn[CPT][kL];
+      if (more) coefs(z + 1, cn);
+      const double *pm = slot[(z - 1) & 3], *pc = slot[z & 3], *pp = slot[(z + 1) & 3];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        int32_t gx, gy;
+        cell_of(u, gx, gy);
+        const int k = cl + u * C;
+        const int hc = ((k / TX) + 1) * HX + k % TX + 1;  // the cell in the halo tile
         double co[7];
         if constexpr (R == 1) {
 #pragma unroll
-          for (int o = 0; o < 7; ++o) co[o] = cur.cv[o];
+          for (int o = 0; o < 7; ++o) co[o] = cv[u][o];
         } else {
           const int base = int(threadIdx.x & 63) & ~(R - 1);
 #pragma unroll
-          for (int o = 0; o < 7; ++o) co[o] = __shfl(cur.cv[o / R], base | (o % R), 64);
+          for (int o = 0; o < 7; ++o) co[o] = __shfl(cv[u][o / R], base | (o % R), 64);
         }
-        const bool valid = cur.lc < nn;
-        const int32_t lcs = valid ? cur.lc : 0;
-        const bool in[7] = {cur.iz > 0,      cur.iy > 0,          cur.ix > 0,         true,
-                            cur.ix < nx - 1, cur.iy < sy.ny - 1, cur.iz < sy.nz - 1};
-        const double xv[7] = {value(cur.zm),  slot(lcs - nx), slot(lcs - 1), slot(lcs),
-                              slot(lcs + 1),  slot(lcs + nx), value(cur.zp)};
+        const double xv[7] = {pm[hc * R + r],        pc[(hc - HX) * R + r], pc[(hc - 1) * R + r],
+                              pc[hc * R + r],        pc[(hc + 1) * R + r],  pc[(hc + HX) * R + r],
+                              pp[hc * R + r]};
+        const bool in[7] = {z > 0, gy > 0, gx > 0, true, gx < nx - 1, gy < ny - 1, z < nz - 1};
         double acc = 0.0;
 #pragma unroll
         for (int o = 0; o < 7; ++o)
           if (in[o]) acc = fma(co[o], xv[o], acc);
-        if (valid) {
-          st_nt(q + (sy.off + cur.lc) * R + r, acc);
+        if (gx < nx && gy < ny) {
+          st_nt(q + (bk.off + gx + int64_t(nx) * gy + nxy * z) * R + r, acc);
           a.add(xv[3], acc);
         }
-        // the window of tile t + 1 is complete after this write
-        if (pf) slot(pc) = value(pv);
-        __syncthreads();
-        pc = pc2;
-        pf = pf2;
-        pv = pv2;
-        if (more) cur = nxt;
       }
-    } else {
-      for (int32_t t = it.t0; t < it.t1; ++t) {
-        const int64_t lc = int64_t(t) * C + cl;
-        if (lc < n) {
-          double pi;
-          const double acc = batch_row(V, sy, lc, r, [&](int64_t e) { return rp[e]; }, value, pi);
-          st_nt(q + (sy.off + lc) * R + r, acc);
-          a.add(pi, acc);
-        }
+      if (pf) put(zn);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u)
+#pragma unroll
+          for (int j = 0; j < kL; ++j) cv[u][j] = cn[u][j];
       }
     }
     DD v[2] = {a.get(), DD{0.0, 0.0}};
     batch_block_reduce<2>(v, R);
-    if (int(threadIdx.x) < R) V.part[(int64_t(it.w) * R + threadIdx.x) * 2] = v[0];
+    if (int(threadIdx.x) < R) V.part1[(int64_t(bk.b) * R + threadIdx.x) * 2] = v[0];
   }
 }
 
@@ -455,7 +459,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin1(BatchView V) {
   const int s = blockIdx.x;
   if (!V.sys_run[s]) return;  // block-uniform
   double t[1];
-  batch_sums<1>(V, V.sys[s], t);
+  const BatchSys sy = V.sys[s];
+  batch_sums<1>(V, V.part1, sy.brick0, sy.brick1, t);
   if (int(threadIdx.x) >= V.nrhs) return;
   BatchCg &c = V.st[s * V.nrhs + threadIdx.x];
   if (c.flag != kRunning) return;
@@ -478,7 +483,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
                                                         const double *__restrict__ q) {
   constexpr int C = kBlock / R, U = 4;
   const int cl = threadIdx.x / R, r = threadIdx.x % R;
-  const Sched sc = my_tiles(*V.nact);
+  const Sched sc = my_tiles(V.nact[0]);
   for (int64_t w = sc.begin; w < sc.end; w += sc.stride) {
     const BatchAct it = V.act[w];
     const BatchSys &sy = it.sy;
@@ -530,7 +535,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin2(BatchView V, int64_t max_
   const int s = blockIdx.x;
   if (!V.sys_run[s]) return;  // block-uniform
   double t[1];
-  batch_sums<1>(V, V.sys[s], t);
+  const BatchSys sy = V.sys[s];
+  batch_sums<1>(V, V.part, sy.item0, sy.item1, t);
   __shared__ int any;
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
@@ -555,41 +561,50 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin2(BatchView V, int64_t max_
   if (threadIdx.x == 0) V.sys_run[s] = any;
 }
 
-// Items of the running systems: exclusive prefix over the systems (one
-// block; thread t takes a contiguous run of systems) and the total, which
-// the host also polls (0 once every system has stopped).
+// Items and bricks of the running systems: exclusive prefixes over the
+// systems (one block; thread t takes a contiguous run of systems) and the
+// totals; the host polls the item total (0 once every system has stopped).
 __global__ void __launch_bounds__(kBlock) k_batch_scan(BatchView V) {
-  __shared__ int32_t part[kBlock];
+  __shared__ int32_t part[2][kBlock];
   const int t = threadIdx.x;
   const int32_t lo = int32_t(int64_t(V.nsys) * t / kBlock), hi = int32_t(int64_t(V.nsys) * (t + 1) / kBlock);
-  int32_t sum = 0;
+  int32_t si = 0, sb = 0;
   for (int32_t u = lo; u < hi; ++u)
-    if (V.sys_run[u]) sum += V.sys[u].item1 - V.sys[u].item0;
-  part[t] = sum;
+    if (V.sys_run[u]) {
+      si += V.sys[u].item1 - V.sys[u].item0;
+      sb += V.sys[u].brick1 - V.sys[u].brick0;
+    }
+  part[0][t] = si;
+  part[1][t] = sb;
   __syncthreads();
-  if (t == 0) {
+  if (t < 2) {
     int32_t acc = 0;
     for (int j = 0; j < kBlock; ++j) {
-      const int32_t v = part[j];
-      part[j] = acc;
+      const int32_t v = part[t][j];
+      part[t][j] = acc;
       acc += v;
     }
-    *V.nact = acc;
+    V.nact[t] = acc;
   }
   __syncthreads();
-  int32_t acc = part[t];
+  int32_t ai = part[0][t], ab = part[1][t];
   for (int32_t u = lo; u < hi; ++u) {
-    V.sys_base[u] = acc;
-    if (V.sys_run[u]) acc += V.sys[u].item1 - V.sys[u].item0;
+    V.sys_base[2 * u] = ai;
+    V.sys_base[2 * u + 1] = ab;
+    if (V.sys_run[u]) {
+      ai += V.sys[u].item1 - V.sys[u].item0;
+      ab += V.sys[u].brick1 - V.sys[u].brick0;
+    }
   }
 }
 
-// The records of the running systems' items (one block per system).
+// The records of the running systems' items and bricks (one block per
+// system).
 __global__ void __launch_bounds__(kBlock) k_batch_compact(BatchView V) {
   const int s = blockIdx.x;
   if (!V.sys_run[s]) return;  // block-uniform
   const BatchSys sy = V.sys[s];
-  const int32_t base = V.sys_base[s];
+  const int32_t base = V.sys_base[2 * s], base1 = V.sys_base[2 * s + 1];
   for (int32_t j = threadIdx.x; j < sy.item1 - sy.item0; j += kBlock) {
     const BatchItem it = V.items[sy.item0 + j];
     BatchAct a;
@@ -599,6 +614,22 @@ __global__ void __launch_bounds__(kBlock) k_batch_compact(BatchView V) {
     a.t0 = it.t0;
     a.t1 = it.t1;
     V.act[base + j] = a;
+  }
+  for (int32_t j = threadIdx.x; j < sy.brick1 - sy.brick0; j += kBlock) {
+    const BatchBrick br = V.bricks[sy.brick0 + j];
+    BatchActB a;
+    a.off = sy.off;
+    a.b = sy.brick0 + j;
+    a.sys = s;
+    a.nx = sy.nx;
+    a.ny = sy.ny;
+    a.nz = sy.nz;
+    a.x0 = br.x0;
+    a.y0 = br.y0;
+    a.z0 = br.z0;
+    a.z1 = br.z1;
+    a.pad = 0;
+    V.act1[base1 + j] = a;
   }
 }
 

@@ -116,9 +116,10 @@ def test_batch_graph_length_and_repeated_solves_agree():
 def test_batch_autotuner_reports_its_choice():
     dims, kc, b, B = _batch(4, 8, lo=8, hi=16, seed=18)
     x, info = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
-    assert info.tiles_per_item in (1, 2, 4, 8, 16, 32) and info.tune_ms > 0
+    assert info.planes_per_brick in (4, 8, 16, 32, 64) and info.tune_ms > 0
+    assert info.tiles_per_item == 16
     x, info2 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
-    assert info2.tiles_per_item == info.tiles_per_item and info2.tune_ms == info.tune_ms
+    assert info2.planes_per_brick == info.planes_per_brick and info2.tune_ms == info.tune_ms
 
 
 def _explicit(dims, nrhs, seed):
@@ -130,35 +131,38 @@ def _explicit(dims, nrhs, seed):
     return dims, k, b, its().Batch(dims, dev(k), nrhs)
 
 
-# The SpMV pass keeps a window of 256/R + 2 nx cells in LDS when it fits
-# (nx <= 768 / R); wider rows gather.  Systems at the limit, just past it,
-# a single cell, and rows shorter than a tile; items of 1, 3 and 16 tiles.
+# The SpMV pass marches bricks of TX x TY cells (R = 8: 16 x 4, 4: 32 x 4,
+# 2: 32 x 8, 1: 64 x 8) through runs of z planes.  Grids one cell short of,
+# equal to and one past a tile edge, a single cell, and z runs of 1, 2, 3
+# and whole columns; work items of 1, 3 and 16 tiles for the update passes.
 @pytest.mark.parametrize("nrhs,dims", [
-    (8, [(96, 4, 3), (97, 3, 2), (5, 7, 3), (1, 1, 1)]),
-    (4, [(192, 2, 3), (193, 2, 2), (3, 9, 2)]),
-    (2, [(384, 1, 3), (385, 2, 1), (1, 1, 1)]),
-    (1, [(768, 2, 1), (769, 1, 2), (2, 3, 40)]),
+    (8, [(16, 4, 3), (17, 5, 2), (15, 3, 7), (1, 1, 1), (33, 9, 4)]),
+    (4, [(32, 4, 2), (33, 5, 3), (31, 3, 5), (3, 9, 2)]),
+    (2, [(32, 8, 3), (33, 9, 2), (1, 1, 1), (5, 17, 4)]),
+    (1, [(64, 8, 2), (65, 9, 1), (63, 7, 3), (2, 3, 40)]),
 ])
-@pytest.mark.parametrize("tiles", [1, 3, 16])
-def test_batch_window_and_gather_rows_bit_exact(nrhs, dims, tiles):
+@pytest.mark.parametrize("tiles,planes", [(1, 1), (3, 2), (16, 3), (16, 0)])
+def test_batch_bricks_bit_exact(nrhs, dims, tiles, planes):
     k = 5
     dims, kc, b, B = _explicit(dims, nrhs, seed=19)
-    B.set_tiles_per_item(tiles)
+    B.set_schedule(tiles, planes)
     x, info = B.solve(dev(b.ravel()), rtol=0.0, max_iter=k)
-    assert info.tiles_per_item == tiles and info.tune_ms == 0.0
+    assert info.tiles_per_item == tiles
+    if planes:
+        assert info.planes_per_brick == planes and info.tune_ms == 0.0
     ref = _oracle_each(dims, kc, b, lambda A, bb: oracle.cg(A, bb, rtol=0.0, max_iter=k)[0])
     for s, part in enumerate(_split(host(x), dims, nrhs)):
         for r in range(nrhs):
             assert np.array_equal(part[:, r], ref[s][r]), (s, r)
 
 
-def test_batch_results_independent_of_item_length():
+def test_batch_results_independent_of_schedule():
     nrhs = 8
     dims, kc, b, B = _batch(5, nrhs, lo=6, hi=30, seed=20)
     bt = dev(b.ravel())
     runs = []
-    for tiles in (1, 2, 7, 32, 0):
-        B.set_tiles_per_item(tiles)
+    for tiles, planes in ((1, 1), (2, 5), (7, 64), (32, 2), (0, 0)):
+        B.set_schedule(tiles, planes)
         x, info = B.solve(bt, rtol=1e-9, max_iter=3000)
         assert info.status == "ok"
         runs.append((host(x), info.iters.copy()))
