@@ -49,7 +49,7 @@ struct BatchItem {
   int32_t pad;
 };
 
-// An item of a running system, as the CG passes read it.
+// An item of a running system, as the update pass reads it.
 struct BatchAct {
   BatchSys sy;
   int32_t w;             // the item's index (its partial slot)
@@ -73,7 +73,7 @@ struct BatchView {
   const double *coef;
   BatchCg *st;
   int32_t *sys_run;  // per system: 1 while any of its right-hand sides runs
-  int32_t *sys_base; // per system: its first slot in act / act1 (running systems)
+  int32_t *sys_base; // [2 s], [2 s + 1]: system s's first slots in act and act1
   int32_t *nact;     // [0] items, [1] bricks of the running systems
   BatchAct *act;     // those items, in system and item order
   BatchActB *act1;   // those bricks, in system and brick order
