@@ -269,9 +269,13 @@ inline int finish_grid(int G) { return G <= kFinishOne ? 0 : (G + kGroup - 1) / 
 
 // ---------------------------------------------------------------- launch size
 
+// One block per tile, except that up to four tiles share a block where that
+// keeps the grid within one finishing level (mid-size vectors, where the
+// second finishing kernel is a noticeable part of an iteration).
 inline int grid_for(int64_t n, int max_blocks = kMaxGrid) {
   int64_t tiles = (n + kBlock - 1) / kBlock;
   if (tiles < 1) tiles = 1;
+  if (tiles > kFinishOne && tiles <= 4 * kFinishOne) tiles = kFinishOne;
   int g = int(tiles < max_blocks ? tiles : max_blocks);
   if (g >= 64) g -= g % kXcds;
   return g;

@@ -538,6 +538,30 @@ def test_full_size_poisson256_packed_cg():
     assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
 
 
+# ------------------------------------------------------------ mid size
+
+@pytest.mark.parametrize("pack", [True, False])
+def test_mid_size_blocks_take_several_tiles(pack):
+    """128^3 Poisson (8192 tiles of 256 rows): the grid is capped at 4096
+    blocks so one finishing kernel suffices, and each block walks two tiles.
+    SpMV, two CG iterations and two Jacobi sweeps against the oracle."""
+    g = (128, 128, 128)
+    print(f"mid size: 128^3 Poisson CSR, pack={pack}", flush=True)
+    Acsr = inputs.poisson7_csr(*g)
+    n = Acsr[0].size - 1
+    A = its().CSRMatrix.from_numpy(*Acsr, validate=False, pack=pack)
+    xs = inputs.uniform_vector(n, 3)
+    b = oracle.spmv(Acsr, xs)
+    bg = its().spmv(A, dev(xs))
+    assert np.array_equal(host(bg), b)
+    ref, rr = oracle.cg(Acsr, b, rtol=0.0, max_iter=2)
+    x, info = its().solve(A, bg, method="cg", rtol=0.0, max_iter=2)
+    assert info.iters == rr.iters == 2 and ulps(host(x), ref) == 0
+    ref, rr = oracle.jacobi(Acsr, b, rtol=0.0, max_iter=2)
+    x, info = its().solve(A, bg, method="jacobi", rtol=0.0, max_iter=2)
+    assert info.iters == rr.iters == 2 and ulps(host(x), ref) == 0
+
+
 # ------------------------------------------------------------ graph replays
 
 @pytest.mark.parametrize("method,kind,extra", [
