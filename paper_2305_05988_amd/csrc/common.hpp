@@ -96,6 +96,7 @@ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v);
 // Two-element vectors for interleaved pairs (one 16- or 8-byte access).
 typedef double double2_t __attribute__((ext_vector_type(2)));
 typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 template <class T> struct Pair;
 template <> struct Pair<double> { using type = double2_t; };
 template <> struct Pair<float> { using type = float2_t; };

@@ -568,7 +568,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
                     const WS &w, its_result *res) {
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
-  const int G = grid_for(n);
+  const int G = grid_for(n), G2 = grid_for(n >> 1);  // G2: row pairs of the FP32 pass 2
   const int dt = o->inner_dtype;
   if (A->kind == kCsr && ((dt == ITS_F32 && !A->val32) || (dt == ITS_F16 && !A->val16)))
     return fail(ITS_E_INVALID, "mixed precision needs its_csr_set_lowp values of that dtype");
@@ -619,8 +619,8 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
           LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
-          LAUNCH(run, 1, k_cg_pass2<float>, G, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
-          FINISH(run, 1, w.R, G, (FinCg2{w.st2}));
+          LAUNCH(run, 1, k_cg_pass2_f32x2, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
+          FINISH(run, 1, w.R, G2, (FinCg2{w.st2}));
           return ITS_OK;
         });
       });

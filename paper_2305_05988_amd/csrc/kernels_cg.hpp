@@ -90,6 +90,60 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   block_partial<1>(v, R);
 }
 
+// Pass 2 of the FP32 inner solve with two rows per thread: the rows' {r, p}
+// pairs move as one 16-byte access and x, q as 8-byte ones, so a wave moves
+// as many bytes per memory instruction as the FP64 pass (one row per thread
+// would halve that and leave the pass instruction-bound).  Row arithmetic is
+// that of k_cg_pass2<float>; the dot partial is exact before its final
+// rounding, so the pairing of rows does not change it.
+__global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__restrict__ x,
+                                                           float2_t *__restrict__ rp,
+                                                           const float *__restrict__ q,
+                                                           const State *st, Reduce *R) {
+  if (st->flag != kRunning) return;
+  const bool first = st->k == 0;
+  const float beta = float(st->beta), alpha = float(st->alpha);
+  Dot2 a;
+  // row with r_i, the old p_i, x_i, q_i: returns the new {r_i, p_i}, updates x_i
+  auto row = [&](float r0, float pold, float &xi, float qi) -> float2_t {
+    const float pi = first ? r0 : fmaT(beta, pold, r0);
+    xi = fmaT(alpha, pi, xi);
+    float2_t o;
+    o.x = fmaT(-alpha, qi, r0);
+    o.y = pi;
+    a.add(double(o.x), double(o.x));
+    return o;
+  };
+  for_rows(n >> 1, [&](int32_t i) {  // rows 2i, 2i + 1
+    const float4_t v = ld_nt(reinterpret_cast<const float4_t *>(rp) + i);
+    const float2_t xv = ld_nt(reinterpret_cast<const float2_t *>(x) + i);
+    const float2_t qv = ld_nt(reinterpret_cast<const float2_t *>(q) + i);
+    float x0 = xv.x, x1 = xv.y;
+    const float2_t o0 = row(v.x, v.y, x0, qv.x);
+    const float2_t o1 = row(v.z, v.w, x1, qv.y);
+    float2_t xo;
+    xo.x = x0;
+    xo.y = x1;
+    float4_t o;
+    o.x = o0.x;
+    o.y = o0.y;
+    o.z = o1.x;
+    o.w = o1.y;
+    st_nt(reinterpret_cast<float2_t *>(x) + i, xo);
+    st_nt(reinterpret_cast<float4_t *>(rp) + i, o);
+  });
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // the last row of an odd n
+    const int32_t i = n - 1;
+    const float2_t v = rp[i];
+    float xi = x[i];
+    const float2_t o = row(v.x, v.y, xi, q[i]);
+    x[i] = xi;
+    rp[i] = o;
+  }
+  DD v[1] = {a.get()};
+  block_partial<1>(v, R);
+}
+
 // rho' = r.r, one more iteration, beta = rho'/rho, convergence test.
 struct FinCg2 {
   State *st;
