@@ -216,7 +216,7 @@ struct Layout {
 //   Jacobi   : x ping-pong buffer (8)
 //   CG       : {r, p} interleaved pairs (16), q (8)
 //   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
-//   BiCGStab : r, r', p0, p1, v0, v1, t (8 each)
+//   BiCGStab : {r, u} pairs (16), r' (8), p (8), {r, v} pairs (16), t (8)
 //   CG-NB    : {r, Ap} interleaved pairs (16), p (8), w = A r (8)
 Layout layout_for(int64_t n, int method, int inner_dtype) {
   Layout L;
@@ -235,7 +235,9 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
         L.nreg = 4; per[0] = 8; per[1] = 8; per[2] = 4; per[3] = 4;
       }
       break;
-    case ITS_BICGSTAB: L.nreg = 7; for (int i = 0; i < 7; ++i) per[i] = 8; break;
+    case ITS_BICGSTAB:
+      L.nreg = 5; per[0] = 16; per[1] = 8; per[2] = 8; per[3] = 16; per[4] = 8;
+      break;
     case ITS_CG_NB: L.nreg = 3; per[0] = 16; per[1] = 8; per[2] = 8; break;
     default: break;
   }
@@ -646,10 +648,10 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
-  double *r = w.v64(0), *rs = w.v64(1), *P[2] = {w.v64(2), w.v64(3)}, *V[2] = {w.v64(4), w.v64(5)},
-         *t = w.v64(6);
+  double2_t *ru = w.reg<double2_t>(0), *rv = w.reg<double2_t>(3);
+  double *rs = w.v64(1), *p = w.v64(2), *t = w.v64(4);
   double bb, rr;
-  its_status s = prologue(run, A, w, b, x, r, 1, h, bb, rr);
+  its_status s = prologue(run, A, w, b, x, reinterpret_cast<double *>(ru), 2, h, bb, rr);
   if (s != ITS_OK) return s;
   if (!std::isfinite(bb)) return fail(ITS_E_INVALID, "b contains NaN or Inf");
   if (bb == 0.0) {
@@ -665,19 +667,18 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   else if (o->max_iter <= 0) flag = kMaxIter;
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
   if (flag == kRunning) {
-    LAUNCH(run, kClassOther, k_bicg_init, G, n, (const double *)r, rs, w.R, std::sqrt(rr));
+    LAUNCH(run, kClassOther, k_bicg_init, G, n, (const double2_t *)ru, rs, w.R, std::sqrt(rr));
     FINISH(run, 1, w.R, G, (FinBicgInit{w.st}));
     const double rt2 = o->restart_tol * o->restart_tol;
     const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
-      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
-        const int a = int(j & 1), c = a ^ 1;
-        LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double *)r, rs, (const double *)P[a], (const double *)V[a], P[c], V[c], (const State *)w.st, w.R);
+      return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
+        LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double2_t *)ru, rs, p, rv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
-        LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double *)r, (const double *)V[c], t, (const State *)w.st, w.R);
+        LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double2_t *)rv, t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
-        LAUNCH(run, 2, k_bicg_c, G, n, x, r, (const double *)rs, (const double *)P[c], (const double *)V[c], (const double *)t, (const State *)w.st, w.R);
+        LAUNCH(run, 2, k_bicg_c, G, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, G, (FinBicgC{w.st, rt2, paper}));
         return ITS_OK;
       });

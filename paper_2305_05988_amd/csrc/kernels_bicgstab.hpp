@@ -8,21 +8,27 @@ namespace its {
 
 // --------------------------------------------------------------- BiCGStab
 // Algorithm 2's arithmetic in three fused passes per iteration:
-//   A: p = r + beta (p - omega v) on the fly (p = r after a restart or at the
-//      start), r' = r/||r|| after a restart, v = A p, alpha_d = v.r'
+//   A: p = r + beta u on the fly (p = r after a restart or at the start),
+//      r' = r/||r|| after a restart, v = A p, alpha_d = v.r'
 //   B: s = r - alpha v on the fly, t = A s, t.s, t.t, omega
-//   C: x = (x + alpha p) + omega s, r = s - omega t, alpha_n' = r.r',
-//      beta = r.r, restart test, convergence test
-// p and v are double-buffered (pass A gathers the old ones).
+//   C: x = (x + alpha p) + omega s, r = s - omega t, u = p - omega v,
+//      alpha_n' = r.r', beta = r.r, restart test, convergence test
+// u = p - omega v is formed in pass C, where omega is already known, so
+// pass A forms p = fma(beta, u, r) -- the same roundings as forming
+// fma(beta, fma(-omega, v, p), r) there.  What the SpMV passes gather is
+// stored as interleaved pairs, one 16-byte access per column: {r, u} for
+// pass A (written by pass C), {r, v} for pass B (written by pass A).
 
-__global__ void __launch_bounds__(kBlock) k_bicg_init(int32_t n, const double *__restrict__ r,
+// r' = r / ||r||, alpha_n = r.r' (r: the first members of the {r, u} pairs)
+__global__ void __launch_bounds__(kBlock) k_bicg_init(int32_t n, const double2_t *__restrict__ ru,
                                                       double *__restrict__ rs, Reduce *R,
                                                       double rnorm) {
   Dot2 a;
   for_rows(n, [&](int32_t i) {
-    const double rsi = r[i] / rnorm;
+    const double ri = ru[i].x;
+    const double rsi = ri / rnorm;
     rs[i] = rsi;
-    a.add(r[i], rsi);
+    a.add(ri, rsi);
   });
   DD v[1] = {a.get()};
   block_partial<1>(v, R);
@@ -35,44 +41,40 @@ struct FinBicgInit {  // alpha_n = r.r'
 };
 
 template <class Op>
-__global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double *__restrict__ r, double *rs,
-                                                   const double *__restrict__ po,
-                                                   const double *__restrict__ vo,
-                                                   double *__restrict__ pn, double *__restrict__ vn,
-                                                   const State *st, Reduce *R) {
+__global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double2_t *__restrict__ ru,
+                                                   double *__restrict__ rs, double *__restrict__ p,
+                                                   double2_t *__restrict__ rv, const State *st,
+                                                   Reduce *R) {
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const bool plain = st->k == 0 || st->restart;
   const bool restart = st->restart;
-  const double bet = st->beta, om = st->omega;
+  const double bet = st->beta;
   const double rn = restart ? __builtin_sqrt(st->rho) : 1.0;
-  // p_j from the loaded {r_j, p_j, v_j} (only r_j when p = r)
-  struct RPV {
-    double r, p, v;
-  };
-  auto load = [&](int32_t j) -> RPV {
-    if (plain) return RPV{r[j], 0.0, 0.0};  // block-uniform
-    return RPV{r[j], po[j], vo[j]};
-  };
-  auto pv = [&](const RPV &e) -> double { return plain ? e.r : fma(bet, fma(-om, e.v, e.p), e.r); };
+  auto load = [&](int32_t j) -> double2_t { return ru[j]; };
+  auto pv = [&](const double2_t &e) -> double { return plain ? e.x : fma(bet, e.y, e.x); };
   Dot2 a;
   A.rows(sm, load, pv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
     double acc = 0.0, pi = 0.0;
     bool have = false;  // p_i taken from the row's diagonal entry
-    entries([&](int32_t j, double av, double p) {
-      acc = fma(av, p, acc);
+    entries([&](int32_t j, double av, double pj) {
+      acc = fma(av, pj, acc);
       if (j == i) {
-        pi = p;
+        pi = pj;
         have = true;
       }
     });
     if (valid) {
       if (!have) pi = own();
-      st_nt(pn + i, pi);
-      st_nt(vn + i, acc);
+      const double ri = ru[i].x;
+      st_nt(p + i, pi);
+      double2_t o;
+      o.x = ri;
+      o.y = acc;
+      st_nt(rv + i, o);
       double rsi;
       if (restart) {
-        rsi = r[i] / rn;
+        rsi = ri / rn;
         rs[i] = rsi;
       } else {
         rsi = rs[i];
@@ -101,19 +103,13 @@ struct FinBicgA {
 };
 
 template <class Op>
-__global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double *__restrict__ r,
-                                                   const double *__restrict__ v,
+__global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double2_t *__restrict__ rv,
                                                    double *__restrict__ t, const State *st,
                                                    Reduce *R) {
   __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   const double alpha = st->alpha;
-  auto load = [&](int32_t j) -> double2_t {
-    double2_t e;
-    e.x = r[j];
-    e.y = v[j];
-    return e;
-  };
+  auto load = [&](int32_t j) -> double2_t { return rv[j]; };
   auto sv = [&](const double2_t &e) -> double { return fma(-alpha, e.y, e.x); };
   Dot2 a0, a1;
   A.rows(sm, load, sv, [&](int32_t i, bool valid, auto &&entries, auto &&own) {
@@ -149,10 +145,11 @@ struct FinBicgB {
   }
 };
 
-__global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict__ x, double *r,
+__global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict__ x,
+                                                   double2_t *__restrict__ ru,
                                                    const double *__restrict__ rs,
                                                    const double *__restrict__ p,
-                                                   const double *__restrict__ v,
+                                                   const double2_t *__restrict__ rv,
                                                    const double *__restrict__ t, const State *st,
                                                    Reduce *R) {
   if (st->flag != kRunning) return;
@@ -160,7 +157,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
   const bool half = (om == 0.0);
   Dot2 a0, a1;
   for_rows(n, [&](int32_t i) {
-    const double si = fma(-alpha, ld_nt(v + i), ld_nt(r + i));
+    const double2_t e = ld_nt(rv + i);  // {r_i, v_i}
+    const double si = fma(-alpha, e.y, e.x);
     const double xi = ld_nt(x + i), pi = ld_nt(p + i), rsi = ld_nt(rs + i);
     double ri;
     if (half) {
@@ -170,7 +168,10 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
       st_nt(x + i, fma(om, si, fma(alpha, pi, xi)));
       ri = fma(-om, ld_nt(t + i), si);
     }
-    st_nt(r + i, ri);
+    double2_t o;
+    o.x = ri;
+    o.y = fma(-om, e.y, pi);  // u = p - omega v
+    st_nt(ru + i, o);
     a0.add(ri, rsi);
     a1.add(ri, ri);
   });
