@@ -31,17 +31,23 @@ struct StencilOp {
     T v[kSlots][kPlane];
   };
 
-  // Brick plan: about 2048 bricks (8 resident blocks on each of 256 CUs),
-  // cutting z into chunks of zb planes.
+  // Brick plan, cutting z into chunks of zb planes: about 4096 bricks where
+  // each still marches at least 16 planes (measured at 256^3: 83 us per CG
+  // SpMV pass against 87 us with 2048 bricks and 90 us with 8192), else
+  // about 2048 (8 resident blocks on each of 256 CUs).
   void plan() {
     nbx = (nx + kTX - 1) / kTX;
     nby = (ny + kTY - 1) / kTY;
     const int64_t nxy = int64_t(nbx) * nby;
-    int64_t chunks = nxy > 0 ? (2048 + nxy - 1) / nxy : 1;
-    if (chunks > nz) chunks = nz;
-    if (chunks < 1) chunks = 1;
-    zb = int32_t((nz + chunks - 1) / chunks);
-    if (zb < 1) zb = 1;
+    auto zb_for = [&](int64_t target) {
+      int64_t chunks = nxy > 0 ? (target + nxy - 1) / nxy : 1;
+      if (chunks > nz) chunks = nz;
+      if (chunks < 1) chunks = 1;
+      const int64_t z = (nz + chunks - 1) / chunks;
+      return int32_t(z < 1 ? 1 : z);
+    };
+    zb = zb_for(4096);
+    if (zb < 16) zb = zb_for(2048);
     nbz = (nz + zb - 1) / zb;
   }
   int grid() const {
