@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -214,6 +215,7 @@ struct Layout {
 
 // Vector regions per method (bytes per row):
 //   Jacobi   : x ping-pong buffer (8)
+//   SGS      : the saved black rows of the iterate under test (8; CSR, two colours)
 //   CG       : {r, p} interleaved pairs (16), q (8)
 //   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
 //   BiCGStab : {r, u} pairs (16), r' (8), p (8), {r, v} pairs (16), t (8)
@@ -227,7 +229,7 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
   int per[8] = {};
   switch (method) {
     case ITS_JACOBI: L.nreg = 1; per[0] = 8; break;
-    case ITS_SGS: L.nreg = 0; break;
+    case ITS_SGS: L.nreg = 1; per[0] = 8; break;
     case ITS_CG:
       if (inner_dtype == ITS_F64) {
         L.nreg = 2; per[0] = 16; per[1] = 8;
@@ -767,37 +769,70 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
   // unchanged inputs, and the next forward sweep's colour 0 repeats this
   // backward sweep's last one; both repeats reproduce identical bits and
   // are skipped.
-  auto sweep = [&](int c) -> its_status {
+  double *xs = w.v64(0);  // CSR, two colours: the black rows of the iterate under test
+  int32_t count[2] = {0, 0};
+  if (A->kind == kCsr)
+    for (int c = 0; c < 2 && c < nc; ++c) count[c] = A->color_off[c + 1] - A->color_off[c];
+  // with two colours both half-sweeps' residual partials line up on one grid
+  const int G2 = grid_for(std::max(count[0], count[1]));
+  auto sweep = [&](int c, auto mode_tag) -> its_status {
+    constexpr int M = decltype(mode_tag)::value;
     if (A->kind == kCsr) {
       const int32_t beg = A->color_off[c], cnt = A->color_off[c + 1] - beg;
-      if (cnt == 0) return ITS_OK;
+      const int Gc = M == kGsPlain ? grid_for(cnt) : G2;
+      if (cnt == 0 && M == kGsPlain) return ITS_OK;
       if (!A->cpack.empty()) {
         const auto &cp = A->cpack[size_t(c)];
-        LAUNCH(run, 0, k_gs_rows_packed, grid_for(cnt), SellOp<double, double>{cp.sp, cp.col, cp.val, cnt}, (const int32_t *)(A->color_rows + beg), b, x, (const State *)w.st);
+        LAUNCH(run, 0, k_gs_rows_packed<M>, Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt}, (const int32_t *)(A->color_rows + beg), b, x, xs, (const State *)w.st, w.R);
         return ITS_OK;
       }
-      LAUNCH(run, 0, k_gs_rows_csr, grid_for(cnt), CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, (const State *)w.st);
+      LAUNCH(run, 0, k_gs_rows_csr<M>, Gc, CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, xs, (const State *)w.st, w.R);
     } else if (A->kind == kSten7) {
       StencilOp<7, double> op{A->nx, A->ny, A->nz, n, {}};
       for (int q = 0; q < 7; ++q) op.c[q] = A->coef[q];
-      LAUNCH(run, 0, k_gs_stencil<7>, G, op, (int32_t)c, b, x, (const State *)w.st);
+      LAUNCH(run, 0, k_gs_stencil<7>, grid_for(gs_colour_cells<7>(A->nx, A->ny, A->nz)), op, (int32_t)c, b, x, (const State *)w.st);
     } else {
       StencilOp<27, double> op{A->nx, A->ny, A->nz, n, {}};
       for (int q = 0; q < 27; ++q) op.c[q] = A->coef[q];
-      LAUNCH(run, 0, k_gs_stencil<27>, G, op, (int32_t)c, b, x, (const State *)w.st);
+      LAUNCH(run, 0, k_gs_stencil<27>, grid_for(gs_colour_cells<27>(A->nx, A->ny, A->nz)), op, (int32_t)c, b, x, (const State *)w.st);
     }
     return ITS_OK;
   };
-  if (flag == kRunning) {
+  using Plain = std::integral_constant<int, kGsPlain>;
+  using Final = std::integral_constant<int, kGsFinal>;
+  using Lagged = std::integral_constant<int, kGsLagged>;
+  if (flag == kRunning && nc == 2 && A->kind == kCsr) {
+    // Iteration 1 sweeps red, black, red; iteration j > 1 black, red.  The
+    // test of iterate j rides on the sweeps: its red residual on iteration
+    // j's last (red) sweep, its black residual on iteration j + 1's black
+    // sweep, after which the test runs; so step j (0-based) finishes
+    // iterate j's test before making iterate j + 1, and max_iter + 1 steps
+    // cover max_iter tests.
+    s = iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
+      its_status e;
+      if (j == 0) {
+        if ((e = sweep(0, Plain{})) != ITS_OK) return e;
+        if ((e = sweep(1, Plain{})) != ITS_OK) return e;
+      } else {
+        if ((e = sweep(1, Lagged{})) != ITS_OK) return e;
+        FINISH(run, 2, w.R, G2, (FinGs2{w.st}));
+      }
+      return sweep(0, Final{});
+    }, /*eager_first=*/true);
+    if (s != ITS_OK) return s;
+    // the stopping test ran after a black sweep: put the tested black rows back
+    LAUNCH(run, kClassOther, k_gs_restore_rows, grid_for(count[1]), (const int32_t *)(A->color_rows + A->color_off[1]), count[1], (const double *)xs, x);
+    HIP_TRY(hipStreamSynchronize(run.s));
+  } else if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t j) -> its_status {
         for (int c = (j == 0 ? 0 : 1); c < nc; ++c) {
-          its_status e = sweep(c);
+          its_status e = sweep(c, Plain{});
           if (e != ITS_OK) return e;
         }
         for (int c = nc - 2; c >= 0; --c) {
-          its_status e = sweep(c);
+          its_status e = sweep(c, Plain{});
           if (e != ITS_OK) return e;
         }
         LAUNCH(run, 1, k_gs_check<decltype(op)>, GA, op, b, (const double *)x, (const State *)w.st, w.R);

@@ -330,6 +330,8 @@ def test_sgs_fixed_k_bit_exact(kind, k):
     x, info = its().solve(A, dev(b), method="sgs", rtol=0.0, max_iter=k)
     assert info.iters == rr.iters == k
     assert np.array_equal(host(x), ref)
+    # the residual of the returned iterate (two colours: formed inside the sweeps)
+    assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
 
 
 def test_sgs_converged_32cube_redblack():
@@ -342,6 +344,7 @@ def test_sgs_converged_32cube_redblack():
     x, info = its().solve(A, dev(b), method="sgs", rtol=1e-8, max_iter=5000)
     assert rr.status == oracle.OK and info.status == "ok" and info.iters == rr.iters
     assert np.array_equal(host(x), ref)
+    assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
     S = its().StencilMatrix(*g, inputs.POISSON7)
     x2, info2 = its().solve(S, dev(b), method="sgs", rtol=1e-8, max_iter=5000)
     assert info2.iters == rr.iters and np.array_equal(host(x2), ref)
