@@ -369,6 +369,29 @@ def test_sgs_packed_colours_in_either_order(pack_first):
     assert np.array_equal(host(x), ref)
 
 
+@pytest.mark.parametrize("pack", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_sgs_two_colours_tiny(pack, n):
+    """Two colours with one row, or an empty black colour: the test inside
+    the sweeps and the restore of the tested black rows at the edges."""
+    rows, cols, vals = [0], [], []
+    for i in range(n):  # tridiagonal (4, -1)
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                cols.append(j)
+                vals.append(4.0 if j == i else -1.0)
+        rows.append(len(cols))
+    Acsr = (np.array(rows), np.array(cols, dtype=np.int32), np.array(vals))
+    col = (np.arange(n) % 2).astype(np.uint8)
+    A = its().CSRMatrix.from_numpy(*Acsr, pack=pack)
+    A.set_colors(col, 2)
+    b = inputs.uniform_vector(n, 3)
+    for rtol, cap in ((0.0, 3), (1e-12, 50)):
+        ref, rr = oracle.sgs(Acsr, col, 2, b, rtol=rtol, max_iter=cap)
+        x, info = its().solve(A, dev(b), method="sgs", rtol=rtol, max_iter=cap)
+        assert info.iters == rr.iters and np.array_equal(host(x), ref), (rtol, cap)
+
+
 def test_sgs_rejects_bad_colouring():
     g = (6, 6, 6)
     Acsr, A = _matrix("csr27", g)
