@@ -1430,7 +1430,7 @@ its_status its_stream_copy(const double *src, double *dst, int64_t n, void *stre
   if (!src || !dst) return fail(ITS_E_INVALID, "null pointer");
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
     return fail(ITS_E_INVALID, "copy buffers must be 16-byte aligned");
-  const int grid = int(std::min<int64_t>((n / 2 + kBlock - 1) / kBlock + 1, 8192));
+  const int grid = int(std::min<int64_t>((n / 2 + kBlock - 1) / kBlock + 1, int64_t(1) << 20));
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kBlock), 0, S(stream), n, src, dst);
   HIP_TRY(hipGetLastError());
   return ITS_OK;
