@@ -298,13 +298,13 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     delete B;
     return its_fail(ITS_E_UNSUPPORTED, "batch too large");
   }
-  B->item_cap = int32_t(std::min<int64_t>(max_tiles_items, int64_t(1) << 30));
   const int64_t max_bricks = count_bricks(B, 1);
-  if (max_bricks >= (int64_t(1) << 30)) {
+  if (max_tiles_items >= (int64_t(1) << 30) || max_bricks >= (int64_t(1) << 30)) {
     delete B;
     return its_fail(ITS_E_UNSUPPORTED, "batch too large");
   }
-  B->brick_cap = int32_t(max_bricks);
+  B->item_cap = int32_t(max_tiles_items);  // items of one tile each at most
+  B->brick_cap = int32_t(max_bricks);      // bricks of one plane each at most
   its_status rs = ITS_OK;
   do {
     if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
