@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <type_traits>
 #include <cmath>
 #include <cstdio>
@@ -427,6 +428,11 @@ its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, in
   }
 }
 
+// Steps of a loop whose step j tests iterate j: one more than the tests.
+int64_t steps_for(int64_t max_iter) {
+  return max_iter < std::numeric_limits<int64_t>::max() ? max_iter + 1 : max_iter;
+}
+
 // Common prologue: zero the States, b.b, r0 = b - A x0 (stored in r if
 // non-null) and r0.r0.  Returns bb and rr0 through `host`.
 its_status prologue(Run &run, const its_matrix *A, const WS &w, const double *b, const double *x,
@@ -722,7 +728,7 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
   // sweep j tests x_j and forms x_{j+1}: max_iter + 1 launches at most
   s = with_op64(A, [&](auto op) -> its_status {
     const int GA = op.grid();
-    return iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
+    return iterate(run, w.st, h, steps_for(o->max_iter), batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
       LAUNCH(run, 0, k_jacobi<decltype(op)>, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
       FINISH(run, 1, w.R, GA, (FinJacobi{w.st}));
@@ -808,7 +814,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
     // sweep, after which the test runs; so step j (0-based) finishes
     // iterate j's test before making iterate j + 1, and max_iter + 1 steps
     // cover max_iter tests.
-    s = iterate(run, w.st, h, o->max_iter + 1, batch_size(o, n), [&](int64_t j) -> its_status {
+    s = iterate(run, w.st, h, steps_for(o->max_iter), batch_size(o, n), [&](int64_t j) -> its_status {
       its_status e;
       if (j == 0) {
         if ((e = sweep(0, Plain{})) != ITS_OK) return e;
