@@ -69,8 +69,11 @@ typedef struct {
                            report the timed launches in its_result */
   int32_t transpose;    /* 1: solve A^T x = b (stencil operators: offsets
                            reflected; variable-coefficient diffusion is
-                           symmetric); ITS_E_UNSUPPORTED for CSR.  Used for
-                           the adjoint solve of a differentiable solve */
+                           symmetric; CSR: the transpose built by
+                           its_csr_transpose, ITS_E_INVALID before it, and
+                           ITS_E_UNSUPPORTED with Gauss-Seidel or mixed
+                           precision).  Used for the adjoint solve of a
+                           differentiable solve */
   int32_t graph;        /* 1: run the iteration loop as a HIP graph of
                            check_every iterations (captured on the first solve
                            with a given matrix, method, vectors and workspace,
@@ -148,6 +151,27 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
    row pointers out of order or range or a bad max_fill; ITS_E_UNSUPPORTED
    (matrix left unpacked) when the bound is exceeded. */
 its_status its_csr_pack(its_matrix *A, double max_fill, void *stream);
+
+/* Builds A^T for transposed solves (its_options.transpose = 1): validates A
+   (as its_csr_validate without the diagonal requirement), then forms A^T in
+   CSR with the rows of each column in ascending order -- unique, so A^T's
+   rows chain exactly as the CSR rows of the transposed matrix -- in device
+   memory the handle owns (n + 1 + nnz int32, nnz float64; freed by
+   its_matrix_destroy or the next call).  If A is packed (now or later), A^T
+   is packed with the same max_fill where its rows fit it (else it stays in
+   CSR form).  Needed for the adjoint of a nonsymmetric CSR solve
+   (the paper's problem statement solves A x = b; this is its adjoint).
+   Synchronises `stream`. */
+its_status its_csr_transpose(its_matrix *A, void *stream);
+
+/* Gradient of a loss L(x) with respect to the stored values of a CSR
+   matrix, where A x = b and lam solves A^T lam = dL/dx (the adjoint solve):
+   dval[k] = -(lam_i x_j) for stored entry k = (i, j).  x, lam: n float64;
+   dval: nnz float64 in A's value order; device, dval must not alias A's
+   values.  A's structure as its_csr_create requires.  Enqueued on `stream`,
+   not synchronised. */
+its_status its_csr_value_grad(const its_matrix *A, const double *x, const double *lam, double *dval,
+                              void *stream);
 
 /* Slots of the packed layout (entries plus padding), 0 if not packed. */
 int64_t its_csr_packed_slots(const its_matrix *A);

@@ -25,7 +25,7 @@ EXPORTS = (
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
     "its_csr_pack", "its_csr_packed_slots", "its_varcoef_create", "its_varcoef_grad",
     "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
-    "its_batch_solve", "its_batch_set_schedule",
+    "its_batch_solve", "its_batch_set_schedule", "its_csr_transpose", "its_csr_value_grad",
 )
 
 
@@ -79,6 +79,8 @@ def load(path: str = LIB_PATH):
         "its_batch_workspace_size": (SZ, [P]),
         "its_batch_solve": (st, [P, P, P, P, P, SZ, P, P, P, P]),
         "its_batch_set_schedule": (st, [P, I32, I32]),
+        "its_csr_transpose": (st, [P, P]),
+        "its_csr_value_grad": (st, [P, P, P, P, P]),
         "its_csr_packed_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),

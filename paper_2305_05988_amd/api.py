@@ -105,6 +105,12 @@ class CSRMatrix(_Matrix):
     def packed_slots(self) -> int:
         return int(L.lib().its_csr_packed_slots(self._h))
 
+    def build_transpose(self):
+        """Builds A^T (device memory owned by the handle) for transposed
+        solves; solve(..., transpose=True) calls it on first use."""
+        L.check(L.lib().its_csr_transpose(self._h, _stream()), "its_csr_transpose")
+        self.has_transpose = True
+
     def set_lowp(self, v):
         if v.dtype == torch.float32:
             dt = L.ITS_F32
@@ -247,6 +253,8 @@ def solve(A, b, x0=None, workspace=None, **opts):
     arguments.  x0 (optional) is copied; pass ``x=`` semantics via x0."""
     b = _vec(b, A.n, "b")
     x = torch.zeros_like(b) if x0 is None else _vec(x0, A.n, "x0").clone()
+    if opts.get("transpose") and isinstance(A, CSRMatrix) and not getattr(A, "has_transpose", False):
+        A.build_transpose()
     o = options(**opts)
     nb = C.c_size_t()
     L.check(L.lib().its_workspace_size(A.handle, C.byref(o), C.byref(nb)), "its_workspace_size")
@@ -313,6 +321,44 @@ class _StencilSolve(torch.autograd.Function):
         if info.status != "ok":
             raise RuntimeError(f"adjoint solve did not converge: {info}")
         return lam, None, None
+
+
+class _CsrSolve(torch.autograd.Function):
+    """x = A^{-1} b for a CSR matrix whose values are a tensor (any method
+    but Gauss-Seidel).  Backward: one adjoint solve A^T lam = dL/dx, then
+    dL/db = lam and dL/dval from the value-gradient kernel."""
+
+    @staticmethod
+    def forward(ctx, val, b, A, opts):
+        x, info = solve(A, b.detach(), **opts)
+        if info.status != "ok":
+            raise RuntimeError(f"forward solve did not converge: {info}")
+        ctx.save_for_backward(x)
+        ctx.A, ctx.opts = A, opts
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        A = ctx.A
+        lam, info = solve(A, gx.contiguous(), transpose=True, **ctx.opts)
+        if info.status != "ok":
+            raise RuntimeError(f"adjoint solve did not converge: {info}")
+        dval = None
+        if ctx.needs_input_grad[0]:
+            dval = torch.empty_like(A.val)
+            L.check(L.lib().its_csr_value_grad(A.handle, _ptr(x), _ptr(lam), _ptr(dval), _stream()),
+                    "its_csr_value_grad")
+        return dval, lam, None, None
+
+
+def csr_solve(A, b, method="bicgstab", rtol=1e-10, max_iter=20000, **opts):
+    """Differentiable solve with a CSR matrix: gradients flow to b and to the
+    stored values A.val (a float64 CUDA tensor; mark it requires_grad) through
+    the transposed (adjoint) solve.  The values must not change while the
+    graph is alive (the handle borrows them)."""
+    o = dict(method=method, rtol=rtol, max_iter=max_iter, **opts)
+    return _CsrSolve.apply(A.val, b, A, o)
 
 
 def stencil_solve(A, b, method="bicgstab", rtol=1e-10, max_iter=20000, **opts):

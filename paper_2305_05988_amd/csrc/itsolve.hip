@@ -54,6 +54,10 @@ struct its_matrix {
     double *val = nullptr;
   };
   std::vector<ColorPack> cpack;
+  // A^T (its_csr_transpose): a CSR handle that owns its arrays (own_*)
+  its_matrix *tr = nullptr;
+  int32_t *own_rp = nullptr, *own_col = nullptr;
+  double *own_val = nullptr;
   // the iteration loop captured as a HIP graph, cached for one argument set
   struct GraphCache {
     hipStream_t s = nullptr;  // own stream: the caller's may be the legacy stream
@@ -995,6 +999,10 @@ its_status its_stencil_create(int32_t nx, int32_t ny, int32_t nz, int32_t npts, 
 
 its_status its_matrix_destroy(its_matrix *A) {
   if (!A) return ITS_OK;
+  if (A->tr) its_matrix_destroy(A->tr);
+  if (A->own_rp) (void)hipFree(A->own_rp);
+  if (A->own_col) (void)hipFree(A->own_col);
+  if (A->own_val) (void)hipFree(A->own_val);
   if (A->color_rows) (void)hipFree(A->color_rows);
   if (A->host_state) (void)hipHostFree(A->host_state);
   free_packed(A);
@@ -1060,6 +1068,92 @@ its_status its_csr_validate(its_matrix *A, int32_t need_diag, void *stream) {
   if (rs != ITS_OK) return rs;
   if (need_diag) A->diag_state = hbad == 0 ? 1 : -1;
   if (hbad) return fail(ITS_E_INVALID, std::to_string(hbad) + " invalid CSR rows");
+  return ITS_OK;
+}
+
+its_status its_csr_transpose(its_matrix *A, void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  its_status rs = its_csr_validate(A, 0, stream);  // columns in range and ascending
+  if (rs != ITS_OK) return rs;
+  drop_graph(A);
+  if (A->tr) {
+    its_matrix_destroy(A->tr);
+    A->tr = nullptr;
+  }
+  its_matrix *T;
+  if ((rs = new_matrix(&T)) != ITS_OK) return rs;
+  T->kind = kCsr;
+  T->n = A->n;
+  T->nnz = A->nnz;
+  const int32_t n = int32_t(A->n);
+  hipStream_t s = S(stream);
+  int32_t *cnt = nullptr;
+  do {
+    if (hipMalloc(&T->own_rp, sizeof(int32_t) * size_t(n + 1)) != hipSuccess ||
+        hipMalloc(&T->own_col, sizeof(int32_t) * size_t(std::max<int64_t>(A->nnz, 1))) != hipSuccess ||
+        hipMalloc(&T->own_val, sizeof(double) * size_t(std::max<int64_t>(A->nnz, 1))) != hipSuccess ||
+        hipMalloc(&cnt, sizeof(int32_t) * size_t(std::max(n, 1))) != hipSuccess) {
+      rs = fail(ITS_E_HIP, "device allocation failed");
+      break;
+    }
+    std::vector<int32_t> h(size_t(n) + 1, 0);
+    if (n > 0) {
+      if (hipMemsetAsync(cnt, 0, sizeof(int32_t) * size_t(n), s) != hipSuccess) {
+        rs = fail(ITS_E_HIP, "memset");
+        break;
+      }
+      hipLaunchKernelGGL(k_tr_count, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rp, A->col, cnt);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(h.data() + 1, cnt, sizeof(int32_t) * size_t(n), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rs = fail(ITS_E_HIP, "column counts");
+        break;
+      }
+    }
+    for (int32_t j = 0; j < n; ++j) h[size_t(j) + 1] += h[size_t(j)];  // row pointers of A^T
+    if (hipMemcpyAsync(T->own_rp, h.data(), sizeof(int32_t) * size_t(n + 1), hipMemcpyHostToDevice, s) != hipSuccess) {
+      rs = fail(ITS_E_HIP, "upload");
+      break;
+    }
+    if (n > 0) {
+      // cursors start at the row starts of A^T
+      if (hipMemcpyAsync(cnt, h.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice, s) != hipSuccess) {
+        rs = fail(ITS_E_HIP, "upload");
+        break;
+      }
+      hipLaunchKernelGGL(k_tr_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, n, A->rp, A->col, A->val, cnt,
+                         T->own_col, T->own_val);
+      hipLaunchKernelGGL(k_tr_sort, dim3(grid_for(n)), dim3(kBlock), 0, s, n, (const int32_t *)T->own_rp,
+                         T->own_col, T->own_val);
+      if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        rs = fail(ITS_E_HIP, "transpose kernels");
+        break;
+      }
+    }
+  } while (0);
+  if (cnt) (void)hipFree(cnt);
+  if (rs != ITS_OK) {
+    its_matrix_destroy(T);
+    return rs;
+  }
+  T->rp = T->own_rp;
+  T->col = T->own_col;
+  T->val = T->own_val;
+  // packed like A where A^T's rows fit the same max_fill (else CSR form)
+  if (A->pack_fill > 0.0) (void)its_csr_pack(T, A->pack_fill, stream);
+  A->tr = T;
+  return ITS_OK;
+}
+
+its_status its_csr_value_grad(const its_matrix *A, const double *x, const double *lam, double *dval,
+                              void *stream) {
+  if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");
+  if (A->n == 0 || A->nnz == 0) return ITS_OK;
+  if (!x || !lam || !dval) return fail(ITS_E_INVALID, "null vector");
+  if (dval == A->val) return fail(ITS_E_INVALID, "dval aliases the matrix values");
+  hipLaunchKernelGGL(k_csr_value_grad, dim3(grid_for(A->n)), dim3(kBlock), 0, S(stream), int32_t(A->n),
+                     A->rp, A->col, x, lam, dval);
+  HIP_TRY(hipGetLastError());
   return ITS_OK;
 }
 
@@ -1225,6 +1319,8 @@ its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
   A->sval16 = P.val16;
   A->sell_entries = P.slots;
   A->pack_fill = max_fill;
+  // A^T alike where its rows fit max_fill (else it stays in CSR form)
+  if (A->tr) (void)its_csr_pack(A->tr, max_fill, stream);
   return pack_colors(A, s);
 }
 
@@ -1341,8 +1437,15 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
   // is A's entry for offset -d, with the same grid truncation); the
   // variable-coefficient operator is symmetric.
   its_matrix At;
-  if (o->transpose == 1 && A->kind != kVar7) {
-    if (A->kind == kCsr) return fail(ITS_E_UNSUPPORTED, "transposed solves need a stencil operator");
+  if (o->transpose == 1 && A->kind == kCsr) {
+    // A^T of a CSR matrix: the handle built by its_csr_transpose
+    if (!A->tr) return fail(ITS_E_INVALID, "transposed CSR solves need its_csr_transpose first");
+    if (o->method == ITS_SGS)
+      return fail(ITS_E_UNSUPPORTED, "Gauss-Seidel with the transpose needs a stencil operator");
+    if (o->inner_dtype != ITS_F64)
+      return fail(ITS_E_UNSUPPORTED, "mixed precision with the transpose needs a stencil operator");
+    A = A->tr;
+  } else if (o->transpose == 1 && A->kind != kVar7) {
     At.kind = A->kind;
     At.n = A->n;
     At.nx = A->nx;

@@ -55,6 +55,70 @@ __global__ void __launch_bounds__(kBlock) k_csr_check(int32_t n, int32_t nnz,
   });
 }
 
+// ------------------------------------------------------ CSR transpose
+// A^T of a validated CSR matrix (columns in range and strictly ascending per
+// row), built in three steps: entries per column (the row lengths of A^T),
+// a scatter that places each entry in its column's range through an atomic
+// cursor (in whatever order the atomics serve), and a per-row sort of A^T by
+// column index, which makes the result unique: row j of A^T lists A's rows
+// with an entry in column j in ascending order, as CSR requires.
+__global__ void __launch_bounds__(kBlock) k_tr_count(int32_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     int32_t *__restrict__ cnt) {
+  for_rows(n, [&](int32_t i) {
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) atomicAdd(cnt + col[k], 1);
+  });
+}
+
+__global__ void __launch_bounds__(kBlock) k_tr_scatter(int32_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
+                                                       int32_t *__restrict__ cursor,
+                                                       int32_t *__restrict__ colT,
+                                                       double *__restrict__ valT) {
+  for_rows(n, [&](int32_t i) {
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t p = atomicAdd(cursor + col[k], 1);
+      colT[p] = i;
+      valT[p] = val[k];
+    }
+  });
+}
+
+// Insertion sort of each row of A^T by column (the entries are distinct).
+__global__ void __launch_bounds__(kBlock) k_tr_sort(int32_t n, const int32_t *__restrict__ rpT,
+                                                    int32_t *__restrict__ colT,
+                                                    double *__restrict__ valT) {
+  for_rows(n, [&](int32_t j) {
+    const int32_t b = rpT[j], e = rpT[j + 1];
+    for (int32_t k = b + 1; k < e; ++k) {
+      const int32_t c = colT[k];
+      const double v = valT[k];
+      int32_t m = k - 1;
+      while (m >= b && colT[m] > c) {
+        colT[m + 1] = colT[m];
+        valT[m + 1] = valT[m];
+        --m;
+      }
+      colT[m + 1] = c;
+      valT[m + 1] = v;
+    }
+  });
+}
+
+// Gradient of a loss with respect to the stored values of A given the
+// solution x and the adjoint lam (A^T lam = dL/dx): dL/da_ij = -lam_i x_j.
+__global__ void __launch_bounds__(kBlock) k_csr_value_grad(int32_t n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ lam,
+                                                           double *__restrict__ dval) {
+  for_rows(n, [&](int32_t i) {
+    const double li = lam[i];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) dval[k] = -(li * x[col[k]]);
+  });
+}
+
 // Colouring check: colour in range, no off-diagonal entry couples two rows
 // of the same colour.
 __global__ void __launch_bounds__(kBlock) k_color_check(int32_t n, const int32_t *__restrict__ rp,

@@ -82,5 +82,7 @@ def test_host_side_argument_errors(lib):
     assert lib.its_batch_create(0, dims, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
     assert lib.its_batch_cells(P0) == -1 and lib.its_batch_workspace_size(P0) == 0
     assert lib.its_batch_set_schedule(P0, 4, 0) == L.ITS_E_INVALID
+    assert lib.its_csr_transpose(P0, P0) == L.ITS_E_INVALID
+    assert lib.its_csr_value_grad(P0, P0, P0, P0, P0) == L.ITS_E_INVALID
     assert lib.its_batch_destroy(P0) == L.ITS_OK
     assert lib.its_csr_packed_slots(P0) == 0

@@ -118,12 +118,27 @@ def test_varcoef_unsupported_paths():
         with pytest.raises(its().ItsError) as e:
             its().solve(A, b, **kw)
         assert e.value.status == -4
-    C = its().CSRMatrix.from_numpy(*Acsr)
-    with pytest.raises(its().ItsError) as e:
-        its().solve(C, b, method="cg", transpose=True)
-    assert e.value.status == -4
+    C = its().CSRMatrix.from_numpy(*Acsr, lowp=("f32",))
     with pytest.raises(its().ItsError):
         its().varcoef_grad(C, b, b)
+    # CSR: transposed solves need its_csr_transpose first (the Python solve
+    # builds it on first use), and not with Gauss-Seidel or mixed precision
+    from paper_2305_05988_amd import _lib as L
+    import ctypes as C_
+    o = its().api.options(method="cg", transpose=True)
+    nb = C_.c_size_t()
+    L.lib().its_workspace_size(C.handle, C_.byref(o), C_.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    x = torch.zeros_like(b)
+    r = L.Result()
+    st = L.lib().its_solve(C.handle, C_.byref(o), C_.c_void_p(b.data_ptr()), C_.c_void_p(x.data_ptr()),
+                           C_.c_void_p(ws.data_ptr()), ws.numel(), None, C_.byref(r))
+    assert st == -1
+    C.set_colors(inputs.redblack_colors(*g), 2)
+    for kw in (dict(method="sgs"), dict(method="cg", inner_dtype="f32")):
+        with pytest.raises(its().ItsError) as e:
+            its().solve(C, b, transpose=True, **kw)
+        assert e.value.status == -4
 
 
 # ------------------------------------------------------------ adjoint solves
@@ -152,6 +167,85 @@ def test_stencil_solve_backward_is_the_transposed_solve():
     At = inputs.stencil_csr(*g, tuple(reversed(c)))
     lam = oracle.lu_solve(oracle.csr_to_dense(At), inputs.uniform_vector(n, 4))
     assert np.max(np.abs(host(b.grad) - lam)) <= 1e-9 * np.max(np.abs(lam))
+
+
+def _transposed(Acsr):
+    import scipy.sparse as sp
+    rp, col, val = Acsr
+    n = rp.size - 1
+    T = sp.csr_matrix((val, col, rp), shape=(n, n)).T.tocsr()
+    T.sort_indices()
+    return (T.indptr.astype(np.int32), T.indices.astype(np.int32), T.data.astype(np.float64))
+
+
+def _ragged_nonsymmetric(n, seed):
+    """Random nonsymmetric CSR with a dominant diagonal, empty off-diagonal
+    rows and columns, and rows of very different lengths."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [0], [], []
+    for i in range(n):
+        m = int(rng.integers(0, 12)) if i % 7 else 0
+        js = sorted(set(int(j) for j in rng.integers(0, n, size=m)) - {i} | {i})
+        for j in js:
+            cols.append(j)
+            vals.append(float(m + 2) if j == i else float(rng.uniform(-1.0, 1.0)))
+        rows.append(len(cols))
+    return (np.array(rows, dtype=np.int32), np.array(cols, dtype=np.int32), np.array(vals))
+
+
+@pytest.mark.parametrize("pack", [False, True])
+@pytest.mark.parametrize("which", ["convdiff", "ragged"])
+def test_transposed_csr_solves_match_oracle(pack, which):
+    if which == "convdiff":
+        Acsr = inputs.convdiff7_csr(11, 9, 7)
+    else:
+        Acsr = _ragged_nonsymmetric(900, 61)
+    At = _transposed(Acsr)
+    A = its().CSRMatrix.from_numpy(*Acsr)
+    if pack:
+        A.pack(max_fill=4.0)
+    b = inputs.uniform_vector(A.n, 5)
+    for method, k in (("bicgstab", 6), ("jacobi", 5)):
+        oracle_fn = {"bicgstab": oracle.bicgstab, "jacobi": oracle.jacobi}[method]
+        ref, rr = oracle_fn(At, b, rtol=0.0, max_iter=k)
+        x, info = its().solve(A, dev(b), method=method, rtol=0.0, max_iter=k, transpose=True)
+        assert info.iters == rr.iters == k, method
+        assert np.array_equal(host(x), ref), method
+
+
+def test_csr_solve_gradients():
+    """dL/db = lam and dL/da_ij = -lam_i x_j with A^T lam = x - xt, against a
+    dense solve, and a few values against central differences."""
+    Acsr = inputs.convdiff7_csr(5, 4, 3)
+    n = Acsr[0].size - 1
+    rp = torch.from_numpy(Acsr[0].astype(np.int32)).cuda()
+    col = torch.from_numpy(Acsr[1].astype(np.int32)).cuda()
+    val = dev(Acsr[2]).requires_grad_(True)
+    A = its().CSRMatrix(rp, col, val)
+    b = dev(inputs.uniform_vector(n, 7)).requires_grad_(True)
+    xt = dev(inputs.uniform_vector(n, 8))
+    x = its().csr_solve(A, b, rtol=1e-14)
+    L = 0.5 * ((x - xt) ** 2).sum()
+    L.backward()
+    D = oracle.csr_to_dense(Acsr)
+    xd = oracle.lu_solve(D, inputs.uniform_vector(n, 7))
+    lam = oracle.lu_solve(D.T.copy(), xd - inputs.uniform_vector(n, 8))
+    rows = np.repeat(np.arange(n), np.diff(Acsr[0]))
+    dval = -lam[rows] * xd[Acsr[1]]
+    assert np.max(np.abs(host(b.grad) - lam)) <= 1e-9 * np.max(np.abs(lam))
+    assert np.max(np.abs(host(val.grad) - dval)) <= 1e-9 * np.max(np.abs(dval))
+    with torch.no_grad():
+        for k in (0, 7, Acsr[1].size // 2, Acsr[1].size - 1):
+            h = 1e-6
+            vals = []
+            for sgn in (1.0, -1.0):
+                v2 = val.detach().clone()
+                v2[k] += sgn * h
+                A2 = its().CSRMatrix(rp, col, v2)
+                x2, _ = its().solve(A2, b.detach(), method="bicgstab", rtol=1e-14, max_iter=5000)
+                vals.append(0.5 * float(((x2 - xt) ** 2).sum()))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - host(val.grad)[k]) <= 1e-6 * np.max(np.abs(dval)), (k, fd)
 
 
 # ------------------------------------------------------------------ autograd
