@@ -257,9 +257,20 @@ __global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, i
   DD v[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) v[d] = DD{0.0, 0.0};
-  for (int j = int(threadIdx.x); j < count; j += kBlock) {
+  // eight partials per thread in flight at a time, added in the same order
+  constexpr int kU = 8;
+  for (int j0 = int(threadIdx.x); j0 < count; j0 += kU * kBlock) {
+    DD t[kU][ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) v[d] = dd_add(v[d], src[d][j]);
+    for (int u = 0; u < kU; ++u) {
+      const int j = j0 + u * kBlock;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) t[u][d] = j < count ? src[d][j] : DD{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int d = 0; d < ND; ++d) v[d] = dd_add(v[d], t[u][d]);
   }
   block_reduce<ND>(v);
   if (threadIdx.x == 0) fin(v);
