@@ -110,7 +110,8 @@ def main():
                     help="device layout of the CSR matrix (packed: its_csr_pack)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
-    ap.add_argument("--extra-only", choices=("batched", "small32", "differentiation"),
+    ap.add_argument("--extra-only",
+                    choices=("batched", "small32", "differentiation", "paper_counts"),
                     help="profiling: run only this secondary workload and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -136,7 +137,8 @@ def main():
         log(f"copy probe: {src.numel() * 8} bytes read, {dst.numel() * 8} bytes written")
         del src, dst
     if args.extra_only:
-        fn = {"batched": batched, "small32": small32, "differentiation": differentiation}
+        fn = {"batched": batched, "small32": small32, "differentiation": differentiation,
+              "paper_counts": paper_counts}
         print(json.dumps({args.extra_only: fn[args.extra_only](its, inputs)}), flush=True)
         return
     N = args.n
@@ -412,6 +414,44 @@ def differentiation(its, inputs):
                                          "adjoint_iters": ai.iters, "backward_s": t_b,
                                          "adjoint_true_rel_res": ai.true_rel_res}
     log(f"differentiation: {json.dumps(out)}")
+    return out
+
+
+# Iteration counts the paper prints for one node (Sec. 3.1): 128 x 128 x 6144
+# cells, b = A 1, x0 = 0, stop when ||r||_2 < 1e-6, BiCGStab restart
+# threshold 1e-5 on sqrt|alpha_n|.
+PAPER_COUNTS = {7: {"bicgstab": 8, "cg": 12, "sgs": 9, "jacobi": 18},
+                27: {"bicgstab": 45, "cg": 72, "sgs": 142, "jacobi": 515}}
+
+
+def paper_counts(its, inputs, grid=(128, 128, 6144)):
+    """Iterations to the paper's absolute criterion on its one-node grid for
+    candidate readings of its matrix (a centred 7- or 27-point stencil with
+    -1 off the diagonal): diagonal 27 on both stencils, 26 on the 27-point
+    one, 6 on the 7-point one (capped).  Matrix-free stencils; the absolute
+    test ||r|| < 1e-6 is the relative one with rtol = 1e-6 / ||b||."""
+    import torch
+    out = {}
+    cases = [(7, 27.0), (7, 6.0), (27, 27.0), (27, 26.0)]
+    for npts, diag in cases:
+        offs = inputs.OFFSETS7 if npts == 7 else inputs.OFFSETS27
+        coef = [diag if o == (0, 0, 0) else -1.0 for o in offs]
+        S = its.StencilMatrix(*grid, coef)
+        b = its.spmv(S, torch.ones(S.n, dtype=torch.float64, device="cuda"))
+        bn = its.dot(b, b) ** 0.5
+        row = {"b_norm": bn, "paper": PAPER_COUNTS[npts]}
+        for method in ("cg", "cgnb", "bicgstab", "sgs", "jacobi"):
+            kw = dict(method=method, rtol=1e-6 / bn, max_iter=2000)
+            if method == "bicgstab":
+                kw.update(restart_mode="paper", restart_tol=1e-5)
+            t, (x, info) = timed(lambda: its.solve(S, b, **kw))
+            row[method] = {"iters": info.iters, "status": info.status, "s": t,
+                           "true_res": info.true_rel_res * bn}
+            del x
+        log(f"paper counts {npts}-point diagonal {diag:g}: {json.dumps(row)}")
+        out[f"{npts}pt_diag{diag:g}"] = row
+        del S, b
+        torch.cuda.empty_cache()
     return out
 
 
