@@ -162,9 +162,13 @@ def main():
     bytes_iter = M + 10 * V
     bytes_pass1 = M + 3 * V  # read col, val, row_ptr, r and p (gathered); write q
     bytes_pass2 = 7 * V      # read x, r, p, q; write x, r, p
-    # bytes the packed layout itself moves in pass 1: padded slots of column
-    # and value, int64 slice offsets, no row pointers
-    moved_pass1 = 12 * slots + 8 * ((n + 63) // 64 + 1) + 3 * V if slots else bytes_pass1
+    # bytes the packed layout itself moves in pass 1: padded value slots,
+    # column indices only in the slices that keep them, the per-position
+    # offset (4 B) and lane mask (8 B) of the offset slices, int64 slice
+    # offsets; no row pointers
+    col_slots = A.packed_column_slots
+    moved_pass1 = (8 * slots + 4 * col_slots + 12 * ((slots - col_slots) // 64)
+                   + 8 * ((n + 63) // 64 + 1) + 3 * V) if slots else bytes_pass1
 
     opts = dict(method="cg", rtol=args.rtol, max_iter=20000)
     if args.fixed_iters:
@@ -198,6 +202,7 @@ def main():
             "frac": bytes_pass1 / avg1 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_pass1, "avg_launch_us": avg1 * 1e6,
             "launches": l1, "kernel_src_sha": sha, "layout_bytes_per_launch": moved_pass1,
+            "layout_column_slots": col_slots, "layout_gbs": moved_pass1 / avg1 / 1e9,
             "update_pass": {"kernel": "k_cg_pass2", "avg_launch_us": avg2 * 1e6,
                             "achieved": bytes_pass2 / avg2 / 1e9}}
     xerr = (x - xs).norm().item() / xs.norm().item()
@@ -210,7 +215,8 @@ def main():
                    "nnz": nnz, "x_star": "U[-1,1) seed 1", "b": "A x*", "x0": 0,
                    "iters_per_solve": info.iters,
                    "device_layout": ("sliced ELLPACK, 64-row slices (its_csr_pack), "
-                                     f"{slots} slots" if slots else "CSR")},
+                                     f"{slots} slots, {col_slots} of them with column "
+                                     "indices" if slots else "CSR")},
         "achieved_gbs": its_per_s * bytes_iter / 1e9,
         "hbm_frac": its_per_s * bytes_iter / 1e9 / HBM_PEAK_GBS,
         "algorithmic_bytes_per_iter": bytes_iter,

@@ -138,12 +138,21 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
    single entries).  Every row keeps its stored entry order, so results are
    bit-identical to the unpacked matrix; the layout spares the row pointers
    and lets each wavefront read two entries of its 64 rows with one
-   coalesced access (the SpMV of Sections 2.1-2.2).
+   coalesced access (the SpMV of Sections 2.1-2.2).  A slice whose rows have
+   strictly ascending columns and take their column offsets (column - row)
+   from one list as long as the slice width stores no column indices at
+   all: one offset and one 64-lane mask per entry position replace them, and
+   each row's entries sit at the positions of their offsets.  Matrices from
+   structured grids (stencils written as CSR) pack entirely this way, which
+   cuts the bytes per FP64 entry from 12 to 8.
    The packed copy (col, val and any low-precision values attached with
    its_csr_set_lowp, which must come first) is allocated and owned by the
    handle and freed by its_matrix_destroy or the next its_csr_pack; it is a
    snapshot, so pack again after changing the values.  Solves and its_spmv
-   use it when present; Gauss-Seidel's colour sweeps keep the CSR arrays.
+   use it when present; with a colouring set (its_csr_set_colors) each
+   colour's rows are packed the same way for Gauss-Seidel's sweeps, and a
+   transpose built with its_csr_transpose is packed too, each where it fits
+   max_fill (else it keeps its CSR arrays).
    Padding slots are streamed like entries, so packing pays only for nearly
    uniform row lengths: max_fill (>= 1) bounds the slots of the rows, the sum
    over slices of (rows in the slice) x (slice width), by
@@ -175,6 +184,11 @@ its_status its_csr_value_grad(const its_matrix *A, const double *x, const double
 
 /* Slots of the packed layout (entries plus padding), 0 if not packed. */
 int64_t its_csr_packed_slots(const its_matrix *A);
+
+/* Slots of the packed layout that store a column index (those of the slices
+   that are not offset slices, see its_csr_pack); 0 if not packed or if
+   every slice is an offset slice. */
+int64_t its_csr_packed_column_slots(const its_matrix *A);
 
 /* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 2.4:
    colours, red-black without rotation).  color: n uint8 (device) with values

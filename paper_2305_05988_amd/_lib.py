@@ -23,7 +23,7 @@ EXPORTS = (
     "its_csr_set_colors", "its_stencil_create", "its_matrix_destroy", "its_matrix_rows",
     "its_spmv", "its_dot_workspace_size", "its_dot", "its_workspace_size", "its_solve",
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
-    "its_csr_pack", "its_csr_packed_slots", "its_varcoef_create", "its_varcoef_grad",
+    "its_csr_pack", "its_csr_packed_slots", "its_csr_packed_column_slots", "its_varcoef_create", "its_varcoef_grad",
     "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
     "its_batch_solve", "its_batch_set_schedule", "its_csr_transpose", "its_csr_value_grad",
 )
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
         "its_csr_transpose": (st, [P, P]),
         "its_csr_value_grad": (st, [P, P, P, P, P]),
         "its_csr_packed_slots": (C.c_int64, [P]),
+        "its_csr_packed_column_slots": (C.c_int64, [P]),
         "its_csr_set_colors": (st, [P, P, I32, P]),
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),
         "its_matrix_destroy": (st, [P]),

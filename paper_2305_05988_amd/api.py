@@ -105,6 +105,11 @@ class CSRMatrix(_Matrix):
     def packed_slots(self) -> int:
         return int(L.lib().its_csr_packed_slots(self._h))
 
+    @property
+    def packed_column_slots(self) -> int:
+        """Packed slots that still store a column index (0: all offset slices)."""
+        return int(L.lib().its_csr_packed_column_slots(self._h))
+
     def build_transpose(self):
         """Builds A^T (device memory owned by the handle) for transposed
         solves; solve(..., transpose=True) calls it on first use."""

@@ -41,17 +41,22 @@ struct its_matrix {
   // Packed copy (its_csr_pack), owned: sliced ELLPACK of col/val and of the
   // low-precision values that were set when it was packed.
   int64_t *sp = nullptr;
-  int32_t *scol = nullptr;
+  int32_t *scol = nullptr;  // null when every slice is an offset slice
   double *sval = nullptr;
   float *sval32 = nullptr;
   __half *sval16 = nullptr;
+  int32_t *soff = nullptr;    // offset-slice descriptors
+  uint64_t *smask = nullptr;
   int64_t sell_entries = 0;
+  int64_t sell_col_slots = 0;  // slots of the slices that store columns
   double pack_fill = 0.0;  // max_fill of the last its_csr_pack (0: not packed)
   // Gauss-Seidel: each colour's rows packed the same way, in colour order
   struct ColorPack {
     int64_t *sp = nullptr;
     int32_t *col = nullptr;
     double *val = nullptr;
+    int32_t *soff = nullptr;
+    uint64_t *smask = nullptr;
   };
   std::vector<ColorPack> cpack;
   // A^T (its_csr_transpose): a CSR handle that owns its arrays (own_*)
@@ -78,6 +83,8 @@ static void free_color_packs(its_matrix *A) {
     if (c.sp) (void)hipFree(c.sp);
     if (c.col) (void)hipFree(c.col);
     if (c.val) (void)hipFree(c.val);
+    if (c.soff) (void)hipFree(c.soff);
+    if (c.smask) (void)hipFree(c.smask);
   }
   A->cpack.clear();
 }
@@ -90,12 +97,17 @@ static void free_packed(its_matrix *A) {
   if (A->sval) (void)hipFree(A->sval);
   if (A->sval32) (void)hipFree(A->sval32);
   if (A->sval16) (void)hipFree(A->sval16);
+  if (A->soff) (void)hipFree(A->soff);
+  if (A->smask) (void)hipFree(A->smask);
   A->sp = nullptr;
   A->scol = nullptr;
   A->sval = nullptr;
   A->sval32 = nullptr;
   A->sval16 = nullptr;
+  A->soff = nullptr;
+  A->smask = nullptr;
   A->sell_entries = 0;
+  A->sell_col_slots = 0;
   A->pack_fill = 0.0;
   free_color_packs(A);
 }
@@ -278,7 +290,9 @@ template <class F>
 its_status with_op64(const its_matrix *A, F &&f) {
   switch (A->kind) {
     case kCsr:
-      if (A->sp) return f(SellOp<double, double>{A->sp, A->scol, A->sval, int32_t(A->n)});
+      if (A->sp && !A->scol)
+        return f(SellOp<double, double, true>{A->sp, A->scol, A->sval, int32_t(A->n), A->soff, A->smask, nullptr});
+      if (A->sp) return f(SellOp<double, double>{A->sp, A->scol, A->sval, int32_t(A->n), A->soff, A->smask, nullptr});
       return f(CsrOp<double, double>{A->rp, A->col, A->val, int32_t(A->n)});
     case kSten7: {
       StencilOp<7, double> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
@@ -306,10 +320,14 @@ its_status with_op32(const its_matrix *A, int dtype, F &&f) {
     case kVar7: return fail(ITS_E_UNSUPPORTED, "mixed precision is not available for variable coefficients");
     case kCsr:
       if (dtype == ITS_F32) {
-        if (A->sp) return f(SellOp<float, float>{A->sp, A->scol, A->sval32, int32_t(A->n)});
+        if (A->sp && !A->scol)
+          return f(SellOp<float, float, true>{A->sp, A->scol, A->sval32, int32_t(A->n), A->soff, A->smask, nullptr});
+        if (A->sp) return f(SellOp<float, float>{A->sp, A->scol, A->sval32, int32_t(A->n), A->soff, A->smask, nullptr});
         return f(CsrOp<float, float>{A->rp, A->col, A->val32, int32_t(A->n)});
       }
-      if (A->sp) return f(SellOp<__half, float>{A->sp, A->scol, A->sval16, int32_t(A->n)});
+      if (A->sp && !A->scol)
+        return f(SellOp<__half, float, true>{A->sp, A->scol, A->sval16, int32_t(A->n), A->soff, A->smask, nullptr});
+      if (A->sp) return f(SellOp<__half, float>{A->sp, A->scol, A->sval16, int32_t(A->n), A->soff, A->smask, nullptr});
       return f(CsrOp<__half, float>{A->rp, A->col, A->val16, int32_t(A->n)});
     case kSten7: {
       StencilOp<7, float> op{A->nx, A->ny, A->nz, int32_t(A->n), {}};
@@ -793,7 +811,7 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
       if (cnt == 0 && M == kGsPlain) return ITS_OK;
       if (!A->cpack.empty()) {
         const auto &cp = A->cpack[size_t(c)];
-        LAUNCH(run, 0, k_gs_rows_packed<M>, Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt}, (const int32_t *)(A->color_rows + beg), b, x, xs, (const State *)w.st, w.R);
+        LAUNCH(run, 0, k_gs_rows_packed<M>, Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, A->color_rows + beg}, (const int32_t *)(A->color_rows + beg), b, x, xs, (const State *)w.st, w.R);
         return ITS_OK;
       }
       LAUNCH(run, 0, k_gs_rows_csr<M>, Gc, CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, xs, (const State *)w.st, w.R);
@@ -1188,13 +1206,18 @@ struct PackOut {
   double *val = nullptr;
   float *val32 = nullptr;
   __half *val16 = nullptr;
+  int32_t *soff = nullptr;
+  uint64_t *smask = nullptr;
   int64_t slots = 0;
+  int64_t col_slots = 0;
   void release() {
     if (sp) (void)hipFree(sp);
     if (col) (void)hipFree(col);
     if (val) (void)hipFree(val);
     if (val32) (void)hipFree(val32);
     if (val16) (void)hipFree(val16);
+    if (soff) (void)hipFree(soff);
+    if (smask) (void)hipFree(smask);
     *this = PackOut();
   }
 };
@@ -1240,23 +1263,45 @@ static its_status pack_rows(const its_matrix *A, const int32_t *rows, int64_t co
                                        std::to_string(entries) + " entries");
   PackOut P;
   hipError_t e = hipMalloc(&P.sp, size_t(ns + 1) * sizeof(int64_t));
-  if (e == hipSuccess && total > 0) e = hipMalloc(&P.col, size_t(total) * sizeof(int32_t));
+  const int64_t cols = total / kSlice;  // entry positions over all slices
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.soff, size_t(cols) * sizeof(int32_t));
+  if (e == hipSuccess && total > 0) e = hipMalloc(&P.smask, size_t(cols) * sizeof(uint64_t));
   if (e == hipSuccess && total > 0) e = hipMalloc(&P.val, size_t(total) * sizeof(double));
   if (e == hipSuccess && total > 0 && lowp && A->val32) e = hipMalloc(&P.val32, size_t(total) * sizeof(float));
   if (e == hipSuccess && total > 0 && lowp && A->val16) e = hipMalloc(&P.val16, size_t(total) * sizeof(__half));
   if (e == hipSuccess)
     e = hipMemcpyAsync(P.sp, hsp.data(), size_t(ns + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  const int32_t ci = int32_t(count);
+  if (e == hipSuccess && total > 0) {
+    // offset slices, then columns for the slices that keep them
+    DevTmp nslots;
+    unsigned long long hslots = 0;
+    e = hipMalloc(&nslots.p, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemsetAsync(nslots.p, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_sell_offsets, dim3(gw), dim3(kBlock), 0, s, ci, A->rp, rows, A->col, P.sp,
+                         P.soff, P.smask, static_cast<unsigned long long *>(nslots.p));
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&hslots, nslots.p, sizeof(hslots), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    P.col_slots = int64_t(hslots);
+    // columns are addressed by slot, so any explicit slice needs the full array
+    if (e == hipSuccess && P.col_slots > 0) e = hipMalloc(&P.col, size_t(total) * sizeof(int32_t));
+  }
   if (e == hipSuccess && total > 0) {
     const int gs = int(std::min<int64_t>((ns * kSlice + kBlock - 1) / kBlock, 65536));
-    const int32_t ci = int32_t(count);
     hipLaunchKernelGGL(k_sell_scatter<double>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
-                       A->val, (const int64_t *)P.sp, P.col, P.val);
+                       A->val, (const int64_t *)P.sp, (const int32_t *)P.soff, P.col, P.val);
     if (P.val32)
       hipLaunchKernelGGL(k_sell_scatter<float>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
-                         A->val32, (const int64_t *)P.sp, (int32_t *)nullptr, P.val32);
+                         A->val32, (const int64_t *)P.sp, (const int32_t *)P.soff, (int32_t *)nullptr,
+                         P.val32);
     if (P.val16)
       hipLaunchKernelGGL(k_sell_scatter<__half>, dim3(gs), dim3(kBlock), 0, s, ci, A->rp, rows, A->col,
-                         A->val16, (const int64_t *)P.sp, (int32_t *)nullptr, P.val16);
+                         A->val16, (const int64_t *)P.sp, (const int32_t *)P.soff, (int32_t *)nullptr,
+                         P.val16);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1285,6 +1330,8 @@ static its_status pack_colors(its_matrix *A, hipStream_t s) {
         if (q.sp) (void)hipFree(q.sp);
         if (q.col) (void)hipFree(q.col);
         if (q.val) (void)hipFree(q.val);
+        if (q.soff) (void)hipFree(q.soff);
+        if (q.smask) (void)hipFree(q.smask);
       }
       if (st == ITS_E_UNSUPPORTED) {
         g_err.clear();
@@ -1296,6 +1343,8 @@ static its_status pack_colors(its_matrix *A, hipStream_t s) {
     cp.sp = P.sp;
     cp.col = P.col;
     cp.val = P.val;
+    cp.soff = P.soff;
+    cp.smask = P.smask;
     packs.push_back(cp);
   }
   A->cpack = packs;
@@ -1317,7 +1366,10 @@ its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
   A->sval = P.val;
   A->sval32 = P.val32;
   A->sval16 = P.val16;
+  A->soff = P.soff;
+  A->smask = P.smask;
   A->sell_entries = P.slots;
+  A->sell_col_slots = P.col_slots;
   A->pack_fill = max_fill;
   // A^T alike where its rows fit max_fill (else it stays in CSR form)
   if (A->tr) (void)its_csr_pack(A->tr, max_fill, stream);
@@ -1325,6 +1377,10 @@ its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
 }
 
 int64_t its_csr_packed_slots(const its_matrix *A) { return A && A->sp ? A->sell_entries : 0; }
+
+int64_t its_csr_packed_column_slots(const its_matrix *A) {
+  return A && A->sp ? A->sell_col_slots : 0;
+}
 
 its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolors, void *stream) {
   if (!A || A->kind != kCsr) return fail(ITS_E_INVALID, "not a CSR matrix");

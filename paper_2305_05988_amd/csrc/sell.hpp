@@ -19,6 +19,23 @@ constexpr int kSlice = 64;  // rows per slice: one wave64
 // A row keeps its entries in stored order; slots past its end hold column
 // -1 (value 0) and are skipped, so the chain is the CSR chain bit for bit.
 // sp has ns + 1 entries (ns = ceil(n / 64)).
+//
+// Offset slices store no columns.  When every row of a slice has strictly
+// ascending columns and all of them draw their column offsets (column minus
+// row) from one ascending list d_0 < ... < d_{w-1} of exactly w offsets, the
+// slice keeps, per entry position j, the offset d_j and a 64-bit mask of the
+// lanes whose row has an entry at offset d_j; a row's entries are laid out
+// at the positions of their offsets (value 0 elsewhere, not consumed).
+// Entry j of such a row is then column row + d_j, in the row's own order, so
+// the chain is unchanged.  The descriptors of slice s sit at positions
+// (sp[s] >> 6) + j of soff / smask, and the slice is flagged by bit 0 of
+// sp[s] (slot bases are multiples of 64).  Structured-grid matrices (the
+// stencils in CSR form) pack entirely into offset slices, which removes the
+// 4-byte column index from every entry's traffic.
+constexpr int64_t kOffsetSlice = 1;
+constexpr int kMaxOffsetWidth = 32;
+__host__ __device__ __forceinline__ int64_t slice_base(int64_t v) { return v & ~int64_t(63); }
+
 __host__ __device__ __forceinline__ int64_t sell_slot(int64_t base, int32_t w, int32_t j,
                                                       int32_t lane) {
   const int32_t c = j >> 1;
@@ -49,12 +66,17 @@ __device__ __forceinline__ void ld_pair(const __half *p, __half &a, __half &b) {
   b = __builtin_bit_cast(__half, static_cast<unsigned short>(v >> 16));
 }
 
-template <class V, class T>
+// OffOnly: every non-empty slice is an offset slice (the layout stores no
+// columns), so the explicit-column path is not compiled in.
+template <class V, class T, bool OffOnly = false>
 struct SellOp {
   const int64_t *__restrict__ sp;
   const int32_t *__restrict__ col;
   const V *__restrict__ val;
   int32_t n;
+  const int32_t *__restrict__ soff;   // offset slices: d_j per entry position
+  const uint64_t *__restrict__ smask;  // offset slices: lanes with an entry at d_j
+  const int32_t *__restrict__ row_of;  // layout row p is matrix row row_of[p] (null: p)
 
   struct Smem {};
 
@@ -67,9 +89,10 @@ struct SellOp {
   // Entries g .. g + W - 1 of the lane's row in a slice of width w (g even):
   // all column and value loads, then all gathers, then the chain.  W is a
   // compile-time constant, so the loads and gathers are straight-line code
-  // and stay in flight together.
-  template <int W, class Fetch, class Consume>
-  __device__ __forceinline__ void group(int64_t base, int32_t w, int32_t g, int lane,
+  // and stay in flight together.  Off: the columns come from the slice's
+  // offsets (row + d_j where the lane's mask bit is set) instead of loads.
+  template <int W, bool Off, class Fetch, class Consume>
+  __device__ __forceinline__ void group(int64_t base, int32_t w, int32_t g, int lane, int32_t row,
                                         int32_t standin, Fetch &&fetch, Consume &&consume) const {
     int32_t cj[W];
     V vj[W];
@@ -77,12 +100,18 @@ struct SellOp {
     for (int c = 0; 2 * c < W; ++c) {
       const int64_t at = sell_slot(base, w, g + 2 * c, lane);
       if (2 * c + 1 < W) {
-        ld_pair(col + at, cj[2 * c], cj[2 * c + 1]);
+        if (!Off) ld_pair(col + at, cj[2 * c], cj[2 * c + 1]);
         ld_pair(val + at, vj[2 * c], vj[2 * c + 1]);
       } else {
-        cj[2 * c] = ld_nt(col + at);
+        if (!Off) cj[2 * c] = ld_nt(col + at);
         vj[2 * c] = ld_nt(val + at);
       }
+    }
+    if (Off) {
+      const int64_t k = (base >> 6) + g;
+#pragma unroll
+      for (int u = 0; u < W; ++u)
+        cj[u] = (smask[k + u] >> lane) & 1u ? row + soff[k + u] : -1;
     }
     // padding slots fetch a stand-in row (not consumed)
     decltype(fetch(0)) xj[W];
@@ -93,6 +122,33 @@ struct SellOp {
       if (cj[u] >= 0) consume(cj[u], T(widen(vj[u])), xj[u]);
   }
 
+  template <bool Off, class Fetch, class Consume>
+  __device__ __forceinline__ void walk(int64_t base, int32_t w, int lane, int32_t row,
+                                       int32_t standin, Fetch &&fetch, Consume &&consume) const {
+    // widths up to 7 (7-point stencils and the like) in one group; wider
+    // slices in groups of 4, which keeps the registers of the widest group
+    // within reach of 6 waves per SIMD
+    switch (w) {  // wave-uniform
+      case 0: return;
+      case 1: group<1, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 2: group<2, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 3: group<3, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 4: group<4, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 5: group<5, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 6: group<6, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      case 7: group<7, Off>(base, w, 0, lane, row, standin, fetch, consume); return;
+      default: break;
+    }
+    int32_t g = 0;
+    for (; g + 4 <= w; g += 4) group<4, Off>(base, w, g, lane, row, standin, fetch, consume);
+    switch (w - g) {
+      case 1: group<1, Off>(base, w, g, lane, row, standin, fetch, consume); break;
+      case 2: group<2, Off>(base, w, g, lane, row, standin, fetch, consume); break;
+      case 3: group<3, Off>(base, w, g, lane, row, standin, fetch, consume); break;
+      default: break;
+    }
+  }
+
   template <class Fetch, class Consume>
   __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &, Fetch &&fetch,
                                                Consume &&consume) const {
@@ -101,30 +157,16 @@ struct SellOp {
     const int32_t s = __builtin_amdgcn_readfirstlane((r0 >> 6) + (int32_t(threadIdx.x) >> 6));
     if (s * kSlice >= r1) return;
     const int lane = threadIdx.x & 63;
-    const int64_t base = sp[s];
-    const int32_t w = int32_t((sp[s + 1] - base) >> 6);
+    const int64_t raw = sp[s];
+    const int64_t base = slice_base(raw);
+    const int32_t w = int32_t((slice_base(sp[s + 1]) - base) >> 6);
     const int32_t standin = s * kSlice;
-    // widths up to 7 (7-point stencils and the like) in one group; wider
-    // slices in groups of 4, which keeps the registers of the widest group
-    // within reach of 6 waves per SIMD
-    switch (w) {  // wave-uniform
-      case 0: return;
-      case 1: group<1>(base, w, 0, lane, standin, fetch, consume); return;
-      case 2: group<2>(base, w, 0, lane, standin, fetch, consume); return;
-      case 3: group<3>(base, w, 0, lane, standin, fetch, consume); return;
-      case 4: group<4>(base, w, 0, lane, standin, fetch, consume); return;
-      case 5: group<5>(base, w, 0, lane, standin, fetch, consume); return;
-      case 6: group<6>(base, w, 0, lane, standin, fetch, consume); return;
-      case 7: group<7>(base, w, 0, lane, standin, fetch, consume); return;
-      default: break;
-    }
-    int32_t g = 0;
-    for (; g + 4 <= w; g += 4) group<4>(base, w, g, lane, standin, fetch, consume);
-    switch (w - g) {
-      case 1: group<1>(base, w, g, lane, standin, fetch, consume); break;
-      case 2: group<2>(base, w, g, lane, standin, fetch, consume); break;
-      case 3: group<3>(base, w, g, lane, standin, fetch, consume); break;
-      default: break;
+    if (OffOnly || (raw & kOffsetSlice)) {
+      const int32_t p = standin + lane;
+      const int32_t row = p < n ? (row_of ? row_of[p] : p) : standin;
+      walk<true>(base, w, lane, row, standin, fetch, consume);
+    } else if (!OffOnly) {
+      walk<false>(base, w, lane, 0, standin, fetch, consume);
     }
   }
 };
@@ -159,15 +201,85 @@ __global__ void __launch_bounds__(kBlock) k_sell_width(int32_t count, int32_t nn
   }
 }
 
+// Decides which slices become offset slices (one thread per slice): builds
+// the sorted list of the column offsets of the slice's rows, and if every
+// row is strictly ascending and the list holds exactly w offsets, writes the
+// offsets and lane masks at (sp[s] >> 6) + j and sets the slice's flag in
+// sp[s].  The slots of the slices that keep explicit columns are added to
+// *col_slots.  sp must hold the unflagged slot bases on entry.
+__global__ void __launch_bounds__(kBlock) k_sell_offsets(int32_t count, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ rows,
+                                                         const int32_t *__restrict__ col, int64_t *sp,
+                                                         int32_t *__restrict__ soff,
+                                                         uint64_t *__restrict__ smask,
+                                                         unsigned long long *col_slots) {
+  const int64_t ns = (int64_t(count) + kSlice - 1) / kSlice;
+  for (int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x; s < ns;
+       s += int64_t(gridDim.x) * kBlock) {
+    const int64_t base = sp[s];
+    const int32_t w = int32_t((slice_base(sp[s + 1]) - base) >> 6);
+    if (w == 0) continue;
+    bool ok = w <= kMaxOffsetWidth;
+    int32_t d[kMaxOffsetWidth];
+    int32_t u = 0;
+    const int32_t p0 = int32_t(s * kSlice);
+    const int32_t p1 = int32_t(min(int64_t(count), (s + 1) * kSlice));
+    for (int32_t p = p0; ok && p < p1; ++p) {
+      const int32_t i = rows ? rows[p] : p;
+      for (int32_t e = rp[i]; ok && e < rp[i + 1]; ++e) {
+        if (e > rp[i] && col[e] <= col[e - 1]) {
+          ok = false;
+          break;
+        }
+        const int32_t o = col[e] - i;
+        int32_t at = 0;  // insertion point in the sorted list
+        while (at < u && d[at] < o) ++at;
+        if (at < u && d[at] == o) continue;
+        if (u == w) {
+          ok = false;
+          break;
+        }
+        for (int32_t q = u; q > at; --q) d[q] = d[q - 1];
+        d[at] = o;
+        ++u;
+      }
+    }
+    if (!ok || u != w) {
+      atomicAdd(col_slots, static_cast<unsigned long long>(kSlice) * unsigned(w));
+      continue;
+    }
+    uint64_t m[kMaxOffsetWidth];
+    for (int32_t j = 0; j < w; ++j) m[j] = 0;
+    for (int32_t p = p0; p < p1; ++p) {
+      const int32_t i = rows ? rows[p] : p;
+      int32_t j = 0;
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        // the row's offsets are in the list, in ascending order
+        while (j < w && d[j] != col[e] - i) ++j;
+        if (j < w) m[j] |= uint64_t(1) << (p - p0);
+      }
+    }
+    const int64_t k = base >> 6;
+    for (int32_t j = 0; j < w; ++j) {
+      soff[k + j] = d[j];
+      smask[k + j] = m[j];
+    }
+    sp[s] = base | kOffsetSlice;
+  }
+}
+
 // Scatters the entries of every row (and the padding of every slot past a
 // row's end, including the rows of the last slice beyond n) into the
-// sliced layout.  col_out may be null to pack values only.
+// sliced layout; in an offset slice a row's entries go to the positions of
+// their offsets and no columns are written.  col_out may be null to pack
+// values only.
 template <class V>
 __global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t count, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ rows,
                                                          const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const int64_t *__restrict__ sp,
+                                                         const int32_t *__restrict__ soff,
                                                          int32_t *__restrict__ col_out,
                                                          V *__restrict__ val_out) {
   const int64_t slots = (int64_t(count) + kSlice - 1) / kSlice * kSlice;
@@ -175,14 +287,25 @@ __global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t count, const in
        p += int64_t(gridDim.x) * kBlock) {
     const int64_t s = p / kSlice;
     const int32_t l = int32_t(p % kSlice);
-    const int64_t base = sp[s];
-    const int32_t w = int32_t((sp[s + 1] - base) / kSlice);
-    int32_t b = 0, len = 0;
+    const int64_t raw = sp[s];
+    const int64_t base = slice_base(raw);
+    const int32_t w = int32_t((slice_base(sp[s + 1]) - base) / kSlice);
+    int32_t b = 0, len = 0, i = 0;
     if (p < count) {
-      const int32_t i = rows ? rows[p] : int32_t(p);
+      i = rows ? rows[p] : int32_t(p);
       b = rp[i];
       len = min(rp[i + 1] - b, w);
       if (len < 0) len = 0;
+    }
+    if (raw & kOffsetSlice) {
+      const int64_t k = base >> 6;
+      int32_t e = 0;
+      for (int32_t j = 0; j < w; ++j) {
+        const bool here = e < len && col[b + e] - i == soff[k + j];
+        val_out[sell_slot(base, w, j, l)] = here ? val[b + e] : V(0.0f);
+        e += here;
+      }
+      continue;
     }
     for (int32_t j = 0; j < w; ++j) {
       const int64_t at = sell_slot(base, w, j, l);

@@ -86,3 +86,4 @@ def test_host_side_argument_errors(lib):
     assert lib.its_csr_value_grad(P0, P0, P0, P0, P0) == L.ITS_E_INVALID
     assert lib.its_batch_destroy(P0) == L.ITS_OK
     assert lib.its_csr_packed_slots(P0) == 0
+    assert lib.its_csr_packed_column_slots(P0) == 0

@@ -117,6 +117,27 @@ def _ragged_csr(n, seed, max_len=13):
     return rp, col, val
 
 
+def _column_slots(rp, col):
+    """Slots of the packed layout that keep column indices: a 64-row slice
+    of width w stores none when its rows have strictly ascending columns
+    whose offsets (column - row) form a set of exactly w values (w <= 32)."""
+    n = rp.size - 1
+    total = 0
+    for s in range(0, n, 64):
+        rows = range(s, min(n, s + 64))
+        w = max(int(rp[i + 1] - rp[i]) for i in rows)
+        if w == 0:
+            continue
+        offs, ok = set(), w <= 32
+        for i in rows:
+            c = col[rp[i]:rp[i + 1]].astype(np.int64)
+            ok = ok and bool(np.all(np.diff(c) > 0))
+            offs |= set((c - i).tolist())
+        if not ok or len(offs) != w:
+            total += 64 * w
+    return total
+
+
 @pytest.mark.parametrize("n,max_len", [(1, 3), (63, 9), (64, 4), (200, 13), (1000, 5), (4099, 30)])
 def test_packed_layout_ragged_rows(n, max_len):
     # empty rows, rows longer than a gather group, a partial last slice
@@ -129,7 +150,56 @@ def test_packed_layout_ragged_rows(n, max_len):
     lens = np.diff(rp)
     widths = [lens[s:s + 64].max() for s in range(0, n, 64)]
     assert slots == 64 * int(np.sum(widths))
+    assert A.packed_column_slots == _column_slots(*Acsr[:2])
     assert np.array_equal(host(its().spmv(A, dev(x))), ref)
+
+
+def _mixed_slices_csr():
+    """A 7-point Poisson CSR on 40 x 8 x 4 (20 slices) with a few rows
+    edited: rows 70 and 700 trade a neighbour for an offset no other row of
+    their slice has (those slices keep columns), row 300 loses one entry and
+    row 1279 (the last) loses its diagonal (both slices stay offset slices)."""
+    rp, col, val = inputs.poisson7_csr(40, 8, 4)
+    rows = [list(zip(col[rp[i]:rp[i + 1]].tolist(), val[rp[i]:rp[i + 1]].tolist()))
+            for i in range(rp.size - 1)]
+
+    def swap(i, old, new, v):
+        r = [e for e in rows[i] if e[0] != old] + [(new, v)]
+        rows[i] = sorted(r)
+
+    swap(70, 71, 73, -0.75)
+    swap(700, 699, 698, 0.5)
+    rows[300] = [e for e in rows[300] if e[0] != 301]
+    rows[1279] = [e for e in rows[1279] if e[0] != 1279]
+    rp2 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col2 = np.array([c for r in rows for c, _ in r], np.int32)
+    val2 = np.array([v for r in rows for _, v in r])
+    return rp2, col2, val2
+
+
+def test_packed_offset_and_column_slices_mixed():
+    Acsr = _mixed_slices_csr()
+    n = Acsr[0].size - 1
+    x = inputs.uniform_vector(n, 5)
+    A = its().CSRMatrix.from_numpy(*Acsr, validate=False, pack=True, max_fill=2.0)
+    expect = _column_slots(*Acsr[:2])
+    # the slices of row 70 (on the z = 0 face: width 6) and row 700 (width 7)
+    assert 0 < expect < A.packed_slots and expect == 64 * (6 + 7)
+    assert A.packed_column_slots == expect
+    assert np.array_equal(host(its().spmv(A, dev(x))), oracle.spmv(Acsr, x))
+    S = its().CSRMatrix.from_numpy(*inputs.poisson7_csr(40, 8, 4), pack=True, max_fill=2.0)
+    assert S.packed_column_slots == 0
+
+
+def test_packed_mixed_slices_cg_and_bicgstab():
+    Acsr = _mixed_slices_csr()
+    b = oracle.spmv(Acsr, inputs.uniform_vector(Acsr[0].size - 1, 6))
+    A = its().CSRMatrix.from_numpy(*Acsr, validate=False, pack=True, max_fill=2.0)
+    for method, ref in (("cg", oracle.cg), ("bicgstab", oracle.bicgstab)):
+        xr, rr = ref(Acsr, b, rtol=0.0, max_iter=5)
+        x, info = its().solve(A, dev(b), method=method, rtol=0.0, max_iter=5)
+        assert info.iters == rr.iters == 5
+        assert np.array_equal(host(x), xr), method
 
 
 def test_packed_layout_all_rows_empty():
