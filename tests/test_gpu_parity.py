@@ -191,6 +191,22 @@ def test_packed_offset_and_column_slices_mixed():
     assert S.packed_column_slots == 0
 
 
+@pytest.mark.parametrize("lo,hi", [(15, 15), (16, 15), (16, 16)])
+def test_packed_band_widths_around_offset_limit(lo, hi):
+    # band rows of 31, 32 and 33 entries: offset slices hold at most 32
+    n = 300
+    rows = [np.arange(max(0, i - lo), min(n, i + hi + 1)) for i in range(n)]
+    rp = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    val = inputs.uniform_vector(col.size, lo + hi)
+    A = its().CSRMatrix.from_numpy(rp, col, val, pack=True, max_fill=2.0)
+    expect = _column_slots(rp, col)
+    assert A.packed_column_slots == expect
+    assert (expect == 0) == (lo + hi + 1 <= 32)
+    x = inputs.uniform_vector(n, 7)
+    assert np.array_equal(host(its().spmv(A, dev(x))), oracle.spmv((rp, col, val), x))
+
+
 def test_packed_mixed_slices_cg_and_bicgstab():
     Acsr = _mixed_slices_csr()
     b = oracle.spmv(Acsr, inputs.uniform_vector(Acsr[0].size - 1, 6))
