@@ -135,7 +135,8 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
    its longest row, column -1 in the slots past a row's end; within a slice
    each row's entries are kept in consecutive pairs (entries 2c and 2c+1 of
    the 64 rows form one contiguous run of 64 pairs; an odd width ends with
-   single entries).  Every row keeps its stored entry order, so results are
+   single entries; the FP32 and FP16 copies use runs of four entries per row,
+   then a pair and a single for the rest).  Every row keeps its stored entry order, so results are
    bit-identical to the unpacked matrix; the layout spares the row pointers
    and lets each wavefront read two entries of its 64 rows with one
    coalesced access (the SpMV of Sections 2.1-2.2).  A slice whose rows have

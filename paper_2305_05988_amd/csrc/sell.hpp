@@ -43,6 +43,26 @@ __host__ __device__ __forceinline__ int64_t sell_slot(int64_t base, int32_t w, i
   return base + 128 * int64_t(c) + int64_t(m) * lane + (j - 2 * c);
 }
 
+// Low-precision values (FP32, FP16) use chunks of four entries per lane
+// instead of two: within a slice of width w the entries 0 .. 4 floor(w/4) - 1
+// form chunks of four (chunk c at base + 256 c + 4 l + {0..3}), a remaining
+// pair sits at base + 64 f + 2 l + {0, 1} (f = 4 floor(w/4)) and a last odd
+// entry at base + 64 (w - 1) + l.  A lane then reads four of its entries
+// with one 16-byte (FP32) or 8-byte (FP16) access.  The FP64 values and the
+// columns keep the pairs of sell_slot.
+__host__ __device__ __forceinline__ int64_t sell_slot4(int64_t base, int32_t w, int32_t j,
+                                                       int32_t lane) {
+  const int32_t f = w / 4 * 4;
+  if (j < f) return base + 64 * int64_t(j & ~3) + 4 * lane + (j & 3);
+  if (w - f >= 2 && j < f + 2) return base + 64 * int64_t(f) + 2 * lane + (j - f);
+  return base + 64 * int64_t(w - 1) + lane;
+}
+template <class V>
+__host__ __device__ __forceinline__ int64_t value_slot(int64_t base, int32_t w, int32_t j,
+                                                       int32_t lane) {
+  return sizeof(V) < 8 ? sell_slot4(base, w, j, lane) : sell_slot(base, w, j, lane);
+}
+
 // Two consecutive values as one load.
 typedef int32_t int2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void ld_pair(const int32_t *p, int32_t &a, int32_t &b) {
@@ -64,6 +84,23 @@ __device__ __forceinline__ void ld_pair(const __half *p, __half &a, __half &b) {
   const uint32_t v = ld_nt(reinterpret_cast<const uint32_t *>(p));
   a = __builtin_bit_cast(__half, static_cast<unsigned short>(v & 0xffffu));
   b = __builtin_bit_cast(__half, static_cast<unsigned short>(v >> 16));
+}
+
+// Four consecutive values as one load.
+typedef uint32_t uint2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void ld_quad(const float *p, float *v) {
+  const float4_t q = ld_nt(reinterpret_cast<const float4_t *>(p));
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ __forceinline__ void ld_quad(const __half *p, __half *v) {
+  const uint2_t q = ld_nt(reinterpret_cast<const uint2_t *>(p));
+  v[0] = __builtin_bit_cast(__half, static_cast<unsigned short>(q.x & 0xffffu));
+  v[1] = __builtin_bit_cast(__half, static_cast<unsigned short>(q.x >> 16));
+  v[2] = __builtin_bit_cast(__half, static_cast<unsigned short>(q.y & 0xffffu));
+  v[3] = __builtin_bit_cast(__half, static_cast<unsigned short>(q.y >> 16));
 }
 
 // OffOnly: every non-empty slice is an offset slice (the layout stores no
@@ -101,11 +138,20 @@ struct SellOp {
       const int64_t at = sell_slot(base, w, g + 2 * c, lane);
       if (2 * c + 1 < W) {
         if (!Off) ld_pair(col + at, cj[2 * c], cj[2 * c + 1]);
-        ld_pair(val + at, vj[2 * c], vj[2 * c + 1]);
+        if (sizeof(V) == 8) ld_pair(val + at, vj[2 * c], vj[2 * c + 1]);
       } else {
         if (!Off) cj[2 * c] = ld_nt(col + at);
-        vj[2 * c] = ld_nt(val + at);
+        if (sizeof(V) == 8) vj[2 * c] = ld_nt(val + at);
       }
+    }
+    if constexpr (sizeof(V) < 8) {
+      // groups start at multiples of 4 and a group shorter than 4 ends the
+      // slice, so the group's chunks are the slice's own
+      constexpr int F = W / 4 * 4;
+#pragma unroll
+      for (int c = 0; 4 * c < F; ++c) ld_quad(val + sell_slot4(base, w, g + 4 * c, lane), vj + 4 * c);
+      if constexpr (W - F >= 2) ld_pair(val + sell_slot4(base, w, g + F, lane), vj[F], vj[F + 1]);
+      if constexpr ((W - F) % 2 == 1) vj[W - 1] = ld_nt(val + sell_slot4(base, w, g + W - 1, lane));
     }
     if (Off) {
       const int64_t k = (base >> 6) + g;
@@ -302,15 +348,14 @@ __global__ void __launch_bounds__(kBlock) k_sell_scatter(int32_t count, const in
       int32_t e = 0;
       for (int32_t j = 0; j < w; ++j) {
         const bool here = e < len && col[b + e] - i == soff[k + j];
-        val_out[sell_slot(base, w, j, l)] = here ? val[b + e] : V(0.0f);
+        val_out[value_slot<V>(base, w, j, l)] = here ? val[b + e] : V(0.0f);
         e += here;
       }
       continue;
     }
     for (int32_t j = 0; j < w; ++j) {
-      const int64_t at = sell_slot(base, w, j, l);
-      if (col_out) col_out[at] = j < len ? col[b + j] : -1;
-      val_out[at] = j < len ? val[b + j] : V(0.0f);
+      if (col_out) col_out[sell_slot(base, w, j, l)] = j < len ? col[b + j] : -1;
+      val_out[value_slot<V>(base, w, j, l)] = j < len ? val[b + j] : V(0.0f);
     }
   }
 }
