@@ -39,8 +39,9 @@ KERNEL_SOURCES = ["paper_2305_05988_amd/csrc/common.hpp", "paper_2305_05988_amd/
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_pass1_poisson256_traffic.txt")
 # Inside the timed region every PROFILE_EVERY-th launch of each kernel is
 # bracketed by HIP events: enough samples for the per-launch average, few
-# enough markers not to perturb the iteration rate.
-PROFILE_EVERY = 8
+# enough markers not to perturb the iteration rate.  Odd, so that the samples
+# alternate between even iterations (whose update pass defers x) and odd ones.
+PROFILE_EVERY = 7
 
 
 def log(*a):
@@ -161,7 +162,9 @@ def main():
     V = 8 * n
     bytes_iter = M + 10 * V
     bytes_pass1 = M + 3 * V  # read col, val, row_ptr, r and p (gathered); write q
-    bytes_pass2 = 7 * V      # read x, r, p, q; write x, r, p
+    # read r, p, q and write r, p every iteration; read and write x every
+    # other iteration (the x update is deferred by one iteration): 6V on average
+    bytes_pass2 = 6 * V
     # bytes the packed layout itself moves in pass 1: padded value slots,
     # column indices only in the slices that keep them, the per-position
     # offset (4 B) and lane mask (8 B) of the offset slices, int64 slice

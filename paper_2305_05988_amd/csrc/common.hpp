@@ -39,6 +39,7 @@ struct alignas(256) State {
   double alpha_d;     // BiCGStab (A p).r'
   double ts, tt;      // BiCGStab (A s).s and (A s).(A s)
   double gamma;       // CG-NB x-update coefficient
+  double alpha_x;     // CG: step of the x update deferred from an even iteration
   double thr2;        // stopping threshold on the squared residual norm
   int64_t max_iter;   // iteration cap
   double dot[4];      // scratch results (dot products, residual norms)

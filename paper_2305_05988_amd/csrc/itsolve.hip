@@ -535,6 +535,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
       });
     });
     if (s != ITS_OK) return s;
+    LAUNCH(run, kClassOther, k_cg_flush_x, G, n, x, (const double2_t *)rp, (const State *)w.st);
   } else {
     s = poll(run, w.st, h);
     if (s != ITS_OK) return s;
@@ -657,6 +658,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
         });
       });
       if (s != ITS_OK) return s;
+      LAUNCH(run, kClassOther, k_cg_flush_x32, G, n, d, (const float2_t *)rhp, (const State *)w.st2);
       inner_total += h->k;
       if (h->flag == kBreakdown) { res->status = ITS_BREAKDOWN; break; }
     }

@@ -40,6 +40,7 @@ __global__ void k_begin(State *st, int32_t flag, double rho, double thr2, int64_
   st->restarts = 0;
   st->rho = rho;
   st->alpha = st->beta = st->omega = 0.0;
+  st->alpha_x = 0.0;
 }
 
 // Dot product x.y (finished by FinDot).

@@ -15,6 +15,14 @@ namespace its {
 //           convergence test, beta = rho'/rho
 // At the first iteration p = r.  r and p are stored interleaved as pairs
 // {r_i, p_i}, so pass 1 gathers both with one access per column.
+//
+// x is read and written every other iteration (both pass 2 kernels): an even
+// iteration k leaves x_k as it is and keeps alpha_k; the odd iteration k + 1,
+// which reads p_k from the pairs anyway, forms
+// x_{k+2} = fma(alpha_{k+1}, p_{k+1}, fma(alpha_k, p_k, x_k)), the same two
+// roundings in the same order as updating x at each iteration.  A solve that
+// stops after an even iteration applies the pending update with k_cg_flush_x
+// (k_cg_flush_x32 for the FP32 inner solve).
 
 template <class Op, class T>
 __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
@@ -70,15 +78,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   using P2 = typename Pair<T>::type;
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
-  const T beta = T(st->beta), alpha = T(st->alpha);
+  const bool defer = (st->k & 1) == 0;  // x waits for the next iteration
+  const T beta = T(st->beta), alpha = T(st->alpha), alpha_x = T(st->alpha_x);
   Dot2 a;
   for_rows(n, [&](int32_t i) {
     const P2 v = ld_nt(rp + i);
     const T r0 = v.x;
     const T pi = first ? r0 : fmaT(beta, v.y, r0);
-    const T xi = ld_nt(x + i);
     const T qi = ld_nt(q + i);
-    st_nt(x + i, fmaT(alpha, pi, xi));
+    if (!defer) {  // v.y is p of the deferred even iteration
+      const T xi = ld_nt(x + i);
+      st_nt(x + i, fmaT(alpha, pi, fmaT(alpha_x, v.y, xi)));
+    }
     const T ri = fmaT(-alpha, qi, r0);
     P2 o;
     o.x = ri;
@@ -88,6 +99,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   });
   DD v[1] = {a.get()};
   block_partial<1>(v, R);
+}
+
+// After the iterations of an FP64 CG solve: an odd count of completed
+// iterations leaves the last one's x update pending (p is still in the
+// pairs); apply it.
+__global__ void __launch_bounds__(kBlock) k_cg_flush_x(int32_t n, double *__restrict__ x,
+                                                       const double2_t *__restrict__ rp,
+                                                       const State *st) {
+  if ((st->k & 1) == 0) return;
+  const double alpha_x = st->alpha_x;
+  for_rows(n, [&](int32_t i) { x[i] = fma(alpha_x, rp[i].y, x[i]); });
+}
+
+// The same for the FP32 inner solve's correction d.
+__global__ void __launch_bounds__(kBlock) k_cg_flush_x32(int32_t n, float *__restrict__ x,
+                                                         const float2_t *__restrict__ rp,
+                                                         const State *st) {
+  if ((st->k & 1) == 0) return;
+  const float alpha_x = float(st->alpha_x);
+  for_rows(n, [&](int32_t i) { x[i] = fmaT(alpha_x, rp[i].y, x[i]); });
 }
 
 // Pass 2 of the FP32 inner solve with two rows per thread: the rows' {r, p}
@@ -102,12 +133,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__r
                                                            const State *st, Reduce *R) {
   if (st->flag != kRunning) return;
   const bool first = st->k == 0;
-  const float beta = float(st->beta), alpha = float(st->alpha);
+  const bool defer = (st->k & 1) == 0;  // x waits for the next iteration, as in k_cg_pass2
+  const float beta = float(st->beta), alpha = float(st->alpha), alpha_x = float(st->alpha_x);
   Dot2 a;
   // row with r_i, the old p_i, x_i, q_i: returns the new {r_i, p_i}, updates x_i
+  // (on odd iterations, with the deferred step of the even one first)
   auto row = [&](float r0, float pold, float &xi, float qi) -> float2_t {
     const float pi = first ? r0 : fmaT(beta, pold, r0);
-    xi = fmaT(alpha, pi, xi);
+    if (!defer) xi = fmaT(alpha, pi, fmaT(alpha_x, pold, xi));
     float2_t o;
     o.x = fmaT(-alpha, qi, r0);
     o.y = pi;
@@ -116,7 +149,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__r
   };
   for_rows(n >> 1, [&](int32_t i) {  // rows 2i, 2i + 1
     const float4_t v = ld_nt(reinterpret_cast<const float4_t *>(rp) + i);
-    const float2_t xv = ld_nt(reinterpret_cast<const float2_t *>(x) + i);
+    float2_t xv = {0.0f, 0.0f};
+    if (!defer) xv = ld_nt(reinterpret_cast<const float2_t *>(x) + i);
     const float2_t qv = ld_nt(reinterpret_cast<const float2_t *>(q) + i);
     float x0 = xv.x, x1 = xv.y;
     const float2_t o0 = row(v.x, v.y, x0, qv.x);
@@ -129,15 +163,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__r
     o.y = o0.y;
     o.z = o1.x;
     o.w = o1.y;
-    st_nt(reinterpret_cast<float2_t *>(x) + i, xo);
+    if (!defer) st_nt(reinterpret_cast<float2_t *>(x) + i, xo);
     st_nt(reinterpret_cast<float4_t *>(rp) + i, o);
   });
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // the last row of an odd n
     const int32_t i = n - 1;
     const float2_t v = rp[i];
-    float xi = x[i];
+    float xi = defer ? 0.0f : x[i];
     const float2_t o = row(v.x, v.y, xi, q[i]);
-    x[i] = xi;
+    if (!defer) x[i] = xi;
     rp[i] = o;
   }
   DD v[1] = {a.get()};
@@ -151,6 +185,7 @@ struct FinCg2 {
   __device__ void operator()(DD (&v)[1]) const {
     const double rho_new = dd_round(v[0]);
     const int64_t k = st->k + 1;
+    if (k & 1) st->alpha_x = st->alpha;  // iteration k - 1 (even) deferred its x update
     st->k = k;
     st->beta = rho_new / st->rho;
     st->rho = rho_new;
