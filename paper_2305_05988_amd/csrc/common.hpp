@@ -22,7 +22,7 @@ constexpr int kXcds = 8;                // MI355X: 8 XCDs, blocks dealt round-ro
 enum : int32_t { kRunning = 0, kConverged = 1, kMaxIter = 2, kBreakdown = 3 };
 
 // Device-resident scalars of one solve.  Kernels read them at entry and the
-// last block of a reducing kernel updates them; the host reads a snapshot
+// finishing kernel of each reduction updates them; the host reads a snapshot
 // only when it polls.
 struct alignas(256) State {
   int32_t flag;       // kRunning / kConverged / kMaxIter / kBreakdown
@@ -30,7 +30,7 @@ struct alignas(256) State {
   int64_t k;          // completed iterations
   int32_t restarts;   // BiCGStab restarts so far
   int32_t pad;
-  uint32_t counter[8];// arrival counters of the last-block reductions
+  uint32_t counter[8];// flags and counters of the setup checks (counter[7]: rows without a diagonal)
   double rho;         // r.r of the current iterate (CG); beta = r.r (BiCGStab)
   double alpha;       // step length
   double beta;        // CG: direction coefficient; BiCGStab: p coefficient

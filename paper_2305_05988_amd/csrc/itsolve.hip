@@ -505,6 +505,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
+  const int G2 = grid_for((int64_t(n) + 1) / 2);  // the update pass: two rows per thread
   double2_t *rp = w.reg<double2_t>(0);  // {r, p} pairs
   double *q = w.v64(1);
   double bb, rr;
@@ -529,8 +530,8 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), GA, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
-        LAUNCH(run, 1, k_cg_pass2<double>, G, n, x, rp, (const double *)q, (const State *)w.st, w.R);
-        FINISH(run, 1, w.R, G, (FinCg2{w.st}));
+        LAUNCH(run, 1, k_cg_pass2<double>, G2, n, x, rp, (const double *)q, (const State *)w.st, w.R);
+        FINISH(run, 1, w.R, G2, (FinCg2{w.st}));
         return ITS_OK;
       });
     });
@@ -680,6 +681,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
+  const int GC = grid_for((int64_t(n) + 1) / 2);  // pass C: two rows per thread
   double2_t *ru = w.reg<double2_t>(0), *rv = w.reg<double2_t>(3);
   double *rs = w.v64(1), *p = w.v64(2), *t = w.v64(4);
   double bb, rr;
@@ -710,8 +712,8 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
         FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
         LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double2_t *)rv, t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
-        LAUNCH(run, 2, k_bicg_c, G, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
-        FINISH(run, 2, w.R, G, (FinBicgC{w.st, rt2, paper}));
+        LAUNCH(run, 2, k_bicg_c, GC, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
+        FINISH(run, 2, w.R, GC, (FinBicgC{w.st, rt2, paper}));
         return ITS_OK;
       });
     });

@@ -156,25 +156,45 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
   const double alpha = st->alpha, om = st->omega;
   const bool half = (om == 0.0);
   Dot2 a0, a1;
-  for_rows(n, [&](int32_t i) {
-    const double2_t e = ld_nt(rv + i);  // {r_i, v_i}
-    const double si = fma(-alpha, e.y, e.x);
-    const double xi = ld_nt(x + i), pi = ld_nt(p + i), rsi = ld_nt(rs + i);
-    double ri;
-    if (half) {
-      st_nt(x + i, fma(alpha, pi, xi));
-      ri = si;
-    } else {
-      st_nt(x + i, fma(om, si, fma(alpha, pi, xi)));
-      ri = fma(-om, ld_nt(t + i), si);
+  // rows i and i + kBlock of each tile of 2 kBlock rows, the loads of both in
+  // flight together (a row past n re-reads row n - 1 and stores nothing)
+  const int64_t ntiles = (int64_t(n) + 2 * kBlock - 1) / (2 * kBlock);
+  const Sched sc = my_tiles(ntiles);
+  for (int64_t k = sc.begin; k < sc.end; k += sc.stride) {
+    int32_t i[2];
+    i[0] = int32_t(k * 2 * kBlock + threadIdx.x);
+    i[1] = i[0] + kBlock;
+    double2_t e[2];
+    double xi[2], pi[2], rsi[2], ti[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t j = min(i[h], n - 1);
+      e[h] = ld_nt(rv + j);  // {r_j, v_j}
+      xi[h] = ld_nt(x + j);
+      pi[h] = ld_nt(p + j);
+      rsi[h] = ld_nt(rs + j);
+      if (!half) ti[h] = ld_nt(t + j);
     }
-    double2_t o;
-    o.x = ri;
-    o.y = fma(-om, e.y, pi);  // u = p - omega v
-    st_nt(ru + i, o);
-    a0.add(ri, rsi);
-    a1.add(ri, ri);
-  });
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (i[h] >= n) continue;
+      const double si = fma(-alpha, e[h].y, e[h].x);
+      double ri;
+      if (half) {
+        st_nt(x + i[h], fma(alpha, pi[h], xi[h]));
+        ri = si;
+      } else {
+        st_nt(x + i[h], fma(om, si, fma(alpha, pi[h], xi[h])));
+        ri = fma(-om, ti[h], si);
+      }
+      double2_t o;
+      o.x = ri;
+      o.y = fma(-om, e[h].y, pi[h]);  // u = p - omega v
+      st_nt(ru + i[h], o);
+      a0.add(ri, rsi[h]);
+      a1.add(ri, ri);
+    }
+  }
   DD d[2] = {a0.get(), a1.get()};
   block_partial<2>(d, R);
 }

@@ -81,22 +81,38 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   const bool defer = (st->k & 1) == 0;  // x waits for the next iteration
   const T beta = T(st->beta), alpha = T(st->alpha), alpha_x = T(st->alpha_x);
   Dot2 a;
-  for_rows(n, [&](int32_t i) {
-    const P2 v = ld_nt(rp + i);
-    const T r0 = v.x;
-    const T pi = first ? r0 : fmaT(beta, v.y, r0);
-    const T qi = ld_nt(q + i);
-    if (!defer) {  // v.y is p of the deferred even iteration
-      const T xi = ld_nt(x + i);
-      st_nt(x + i, fmaT(alpha, pi, fmaT(alpha_x, v.y, xi)));
+  // rows i and i + kBlock of each tile of 2 kBlock rows, the loads of both in
+  // flight together (a row past n re-reads row n - 1 and stores nothing)
+  const int64_t ntiles = (int64_t(n) + 2 * kBlock - 1) / (2 * kBlock);
+  const Sched sc = my_tiles(ntiles);
+  for (int64_t t = sc.begin; t < sc.end; t += sc.stride) {
+    int32_t i[2];
+    i[0] = int32_t(t * 2 * kBlock + threadIdx.x);
+    i[1] = i[0] + kBlock;
+    P2 v[2];
+    T qi[2], xi[2] = {T(0), T(0)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int32_t j = min(i[h], n - 1);
+      v[h] = ld_nt(rp + j);
+      qi[h] = ld_nt(q + j);
+      if (!defer) xi[h] = ld_nt(x + j);
     }
-    const T ri = fmaT(-alpha, qi, r0);
-    P2 o;
-    o.x = ri;
-    o.y = pi;
-    st_nt(rp + i, o);
-    a.add(double(ri), double(ri));
-  });
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (i[h] >= n) continue;
+      const T r0 = v[h].x;
+      const T pi = first ? r0 : fmaT(beta, v[h].y, r0);
+      // on odd iterations v.y is p of the deferred even iteration
+      if (!defer) st_nt(x + i[h], fmaT(alpha, pi, fmaT(alpha_x, v[h].y, xi[h])));
+      const T ri = fmaT(-alpha, qi[h], r0);
+      P2 o;
+      o.x = ri;
+      o.y = pi;
+      st_nt(rp + i[h], o);
+      a.add(double(ri), double(ri));
+    }
+  }
   DD v[1] = {a.get()};
   block_partial<1>(v, R);
 }
