@@ -648,6 +648,12 @@ def test_full_size_poisson256_packed_cg():
     assert info.iters == rr.iters == 2
     assert ulps(xg, ref) == 0
     assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
+    # an odd count: the last iteration's x update is applied after the loop
+    print("full size: oracle CG, 3 iterations", flush=True)
+    ref, rr = oracle.cg(Acsr, b, rtol=0.0, max_iter=3)
+    x, info = its().solve(A, bg, method="cg", rtol=0.0, max_iter=3)
+    assert info.iters == rr.iters == 3
+    assert ulps(host(x), ref) == 0
 
 
 # ------------------------------------------------------------ mid size
