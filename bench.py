@@ -13,6 +13,10 @@ the library on their workloads.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras] [--no-cpu]
                     [--layout packed|csr]
+    python bench.py --extra-only batched|small32|differentiation|paper_counts
+
+paper_counts is not part of the default run: it reproduces the paper's
+one-node iteration counts (Sec. 3.1) for candidate readings of its matrix.
 """
 from __future__ import annotations
 
