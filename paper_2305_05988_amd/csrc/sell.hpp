@@ -117,7 +117,10 @@ struct SellOp {
 
   struct Smem {};
 
-  int grid() const { return grid_for(n); }
+  // FP32/FP16 passes move few bytes per tile, so per-block costs weigh more:
+  // their blocks walk several tiles (and one finishing kernel suffices);
+  // FP64 passes keep one tile per block
+  int grid() const { return sizeof(V) < 8 ? grid_for(n, kFinishOne) : grid_for(n); }
   template <class Load, class Value, class Body>
   __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
     tiled_rows(*this, sm, load, value, body);
