@@ -505,7 +505,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
-  const int G2 = grid_for((int64_t(n) + 1) / 2);  // the update pass: two rows per thread
+  const int G2 = grid_for((int64_t(n) + 1) / 2, kFinishOne);  // the update pass: two rows per thread
   double2_t *rp = w.reg<double2_t>(0);  // {r, p} pairs
   double *q = w.v64(1);
   double bb, rr;
@@ -602,7 +602,7 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
                     const WS &w, its_result *res) {
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
-  const int G = grid_for(n), G2 = grid_for(n >> 1);  // G2: row pairs of the FP32 pass 2
+  const int G = grid_for(n), G2 = grid_for(n >> 1, kFinishOne);  // G2: row pairs of the FP32 pass 2
   const int dt = o->inner_dtype;
   if (A->kind == kCsr && ((dt == ITS_F32 && !A->val32) || (dt == ITS_F16 && !A->val16)))
     return fail(ITS_E_INVALID, "mixed precision needs its_csr_set_lowp values of that dtype");
@@ -681,7 +681,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   State *h = A->host_state;
   const int32_t n = int32_t(A->n);
   const int G = grid_for(n);
-  const int GC = grid_for((int64_t(n) + 1) / 2);  // pass C: two rows per thread
+  const int GC = grid_for((int64_t(n) + 1) / 2, kFinishOne);  // pass C: two rows per thread
   double2_t *ru = w.reg<double2_t>(0), *rv = w.reg<double2_t>(3);
   double *rs = w.v64(1), *p = w.v64(2), *t = w.v64(4);
   double bb, rr;
