@@ -815,7 +815,11 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
       if (cnt == 0 && M == kGsPlain) return ITS_OK;
       if (!A->cpack.empty()) {
         const auto &cp = A->cpack[size_t(c)];
-        LAUNCH(run, 0, k_gs_rows_packed<M>, Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, A->color_rows + beg}, (const int32_t *)(A->color_rows + beg), b, x, xs, (const State *)w.st, w.R);
+        const int32_t *rows = A->color_rows + beg;
+        if (!cp.col)  // every slice an offset slice
+          LAUNCH(run, 0, (k_gs_rows_packed<M, SellOp<double, double, true>>), Gc, SellOp<double, double, true>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, rows}, rows, b, x, xs, (const State *)w.st, w.R);
+        else
+          LAUNCH(run, 0, (k_gs_rows_packed<M, SellOp<double, double>>), Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, rows}, rows, b, x, xs, (const State *)w.st, w.R);
         return ITS_OK;
       }
       LAUNCH(run, 0, k_gs_rows_csr<M>, Gc, CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, xs, (const State *)w.st, w.R);

@@ -119,13 +119,12 @@ __global__ void __launch_bounds__(kBlock) k_gs_rows_csr(CsrOp<double, double> A,
 
 // The same half-sweep over a colour's rows in their own packed layout (row p
 // of the layout is rows[p]), so the entries stream coalesced.
-template <int Mode>
-__global__ void __launch_bounds__(kBlock) k_gs_rows_packed(SellOp<double, double> A,
-                                                           const int32_t *__restrict__ rows,
+template <int Mode, class Op>
+__global__ void __launch_bounds__(kBlock) k_gs_rows_packed(Op A, const int32_t *__restrict__ rows,
                                                            const double *__restrict__ b, double *x,
                                                            double *__restrict__ xs,
                                                            const State *st, Reduce *R) {
-  __shared__ SellOp<double, double>::Smem sm;
+  __shared__ typename Op::Smem sm;
   if (st->flag != kRunning) return;
   auto xj = [&](int32_t j) { return x[j]; };
   Dot2 a;
