@@ -59,6 +59,7 @@ struct BatchAct {
 // CG scalars of one (system, right-hand side).
 struct BatchCg {
   double rho, alpha, beta, bb, thr2;
+  double alpha_x;  // step of the x update deferred from an even iteration
   int64_t k;
   int32_t flag;
   int32_t zero_b;
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_begin(BatchView V, int64_t max
   if (int(threadIdx.x) < V.nrhs) {
     BatchCg &c = V.st[s * V.nrhs + threadIdx.x];
     c.k = 0;
-    c.alpha = c.beta = 0.0;
+    c.alpha = c.beta = c.alpha_x = 0.0;
     c.zero_b = c.bb == 0.0;
     if (c.zero_b)
       c.flag = kConverged;
@@ -490,7 +491,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
     const BatchCg &c = V.st[it.sys * R + r];
     const bool run = c.flag == kRunning;
     const bool first = c.k == 0;
-    const double beta = c.beta, alpha = c.alpha;
+    // x is read and written on odd iterations only, with the deferred update
+    // of the even one first (the same roundings as updating it every time)
+    const bool defer = (c.k & 1) == 0;
+    const double beta = c.beta, alpha = c.alpha, alpha_x = c.alpha_x;
     const int64_t n = int64_t(sy.nx) * sy.ny * sy.nz;
     const int64_t e0 = sy.off * R + r;
     const int32_t P = sy.item1 - sy.item0, j = it.w - sy.item0;
@@ -507,14 +511,14 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
         ok[u] = run && tt < sy.tiles && lc < n;
         e[u] = e0 + (ok[u] ? lc : 0) * R;
         v[u] = ld_nt(rp + e[u]);
-        xo[u] = ld_nt(x + e[u]);
+        xo[u] = defer ? 0.0 : ld_nt(x + e[u]);
         qo[u] = ld_nt(q + e[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (!ok[u]) continue;
         const double pi = first ? v[u].x : fma(beta, v[u].y, v[u].x);
-        st_nt(x + e[u], fma(alpha, pi, xo[u]));
+        if (!defer) st_nt(x + e[u], fma(alpha, pi, fma(alpha_x, v[u].y, xo[u])));
         const double ri = fma(-alpha, qo[u], v[u].x);
         double2_t o;
         o.x = ri;
@@ -526,6 +530,21 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
     DD v[2] = {a.get(), DD{0.0, 0.0}};
     batch_block_reduce<2>(v, R);
     if (int(threadIdx.x) < R) V.part[(int64_t(it.w) * R + threadIdx.x) * 2] = v[0];
+  }
+}
+
+// After the iterations: a (system, rhs) that stopped after an odd count of
+// iterations still owes the x update of its last (even) iteration, whose p
+// is in the pairs.  One block per system.
+__global__ void __launch_bounds__(kBlock) k_batch_flush_x(BatchView V, double *__restrict__ x,
+                                                          const double2_t *__restrict__ rp) {
+  const int s = blockIdx.x;
+  const BatchSys sy = V.sys[s];
+  const int R = V.nrhs;
+  const int64_t e0 = sy.off * R, e1 = (sy.off + int64_t(sy.nx) * sy.ny * sy.nz) * R;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    const BatchCg &c = V.st[int64_t(s) * R + (e - e0) % R];
+    if (c.k & 1) x[e] = fma(c.alpha_x, rp[e].y, x[e]);
   }
 }
 
@@ -545,6 +564,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_fin2(BatchView V, int64_t max_
     if (c.flag == kRunning) {
       const double rho_new = t[0];
       const int64_t k = c.k + 1;
+      if (k & 1) c.alpha_x = c.alpha;  // iteration k - 1 (even) deferred its x update
       c.k = k;
       c.beta = rho_new / c.rho;
       c.rho = rho_new;
