@@ -475,7 +475,7 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
       if (replays > max_replays) return its_fail(ITS_E_HIP, "batched solve still running after max_iter");
     }
   }
-  hipLaunchKernelGGL(k_batch_flush_x, dim3(S), dim3(kBlock), 0, s, V, x, (const double2_t *)pairs);
+  hipLaunchKernelGGL(k_batch_flush_x, dim3(S, kFlushParts), dim3(kBlock), 0, s, V, x, (const double2_t *)pairs);
   BHIP(hipGetLastError());
   BHIP(hipMemcpyAsync(hst.data(), V.st, hst.size() * sizeof(BatchCg), hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));

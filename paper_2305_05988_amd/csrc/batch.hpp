@@ -535,17 +535,21 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
 
 // After the iterations: a (system, rhs) that stopped after an odd count of
 // iterations still owes the x update of its last (even) iteration, whose p
-// is in the pairs.  One block per system.
+// is in the pairs.  Grid: (systems, kFlushParts) blocks; the stride of a
+// thread is a multiple of the rhs count, so each thread serves one rhs.
+constexpr int kFlushParts = 32;
 __global__ void __launch_bounds__(kBlock) k_batch_flush_x(BatchView V, double *__restrict__ x,
                                                           const double2_t *__restrict__ rp) {
   const int s = blockIdx.x;
   const BatchSys sy = V.sys[s];
   const int R = V.nrhs;
+  const BatchCg &c = V.st[int64_t(s) * R + int(threadIdx.x) % R];
+  if ((c.k & 1) == 0) return;
+  const double alpha_x = c.alpha_x;
   const int64_t e0 = sy.off * R, e1 = (sy.off + int64_t(sy.nx) * sy.ny * sy.nz) * R;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-    const BatchCg &c = V.st[int64_t(s) * R + (e - e0) % R];
-    if (c.k & 1) x[e] = fma(c.alpha_x, rp[e].y, x[e]);
-  }
+  for (int64_t e = e0 + int64_t(blockIdx.y) * kBlock + threadIdx.x; e < e1;
+       e += int64_t(kBlock) * kFlushParts)
+    x[e] = fma(alpha_x, rp[e].y, x[e]);
 }
 
 // rho' = r.r, one more iteration, beta = rho'/rho, test; the system stays
