@@ -346,9 +346,10 @@ def batched(its, inputs, nsys=512, nrhs=8):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     it = info.iters
-    # bytes actually needed: per (system, rhs) iteration 10 vector touches of 8 B per cell;
+    # bytes actually needed: per (system, rhs) iteration 9 vector touches of 8 B per cell on
+    # average (x is read and written every other iteration);
     # per system iteration the 7 coefficients (56 B per cell) once for all right-hand sides
-    vec_bytes = float(np.sum(it * n_s[:, None]) * 80)
+    vec_bytes = float(np.sum(it * n_s[:, None]) * 72)
     coef_bytes = float(np.sum(it.max(axis=1) * n_s) * 56)
     out = {"systems": nsys, "rhs": nrhs, "cells": int(n_s.sum()), "setup_s": setup,
            "status": info.status, "solve_s": dt, "first_solve_s": first.solve_ms / 1e3,
