@@ -16,7 +16,7 @@ the library on their workloads.
     python bench.py --extra-only batched|small32|differentiation|paper_counts
 
 paper_counts is not part of the default run: it reproduces the paper's
-one-node iteration counts (Sec. 3.1) for candidate readings of its matrix.
+one-node iteration counts (Sec. 4.1) for candidate readings of its matrix.
 """
 from __future__ import annotations
 
@@ -431,7 +431,7 @@ def differentiation(its, inputs):
     return out
 
 
-# Iteration counts the paper prints for one node (Sec. 3.1): 128 x 128 x 6144
+# Iteration counts the paper prints for one node (Sec. 4.1): 128 x 128 x 6144
 # cells, b = A 1, x0 = 0, stop when ||r||_2 < 1e-6, BiCGStab restart
 # threshold 1e-5 on sqrt|alpha_n|.
 PAPER_COUNTS = {7: {"bicgstab": 8, "cg": 12, "sgs": 9, "jacobi": 18},

@@ -5,10 +5,10 @@
  * gradient or BiCGStab, to a relative-residual tolerance within a maximum
  * iteration count -- the problem statement of Martinez-Ferrer, Arslan and
  * Beltran, "Improving the performance of classical linear algebra iterative
- * methods via hybrid parallelism" (JPDC 2023), Section 2.1.  A is given in
- * CSR (the format of the HPCCG code the paper builds on, Section 2.2) or as
+ * methods via hybrid parallelism" (JPDC 2023), Section 3.1.  A is given in
+ * CSR (the format of the HPCCG code the paper builds on, Section 3.2) or as
  * a constant-coefficient 7- or 27-point stencil on a structured 3-D grid (the
- * paper's two sparsity patterns, Section 2.1).
+ * paper's two sparsity patterns, Section 3.1).
  *
  * Conventions for every entry point:
  *  - Device pointers are HIP device memory on the current device; "host"
@@ -109,7 +109,7 @@ void its_default_options(its_options *opts /* host, out */);
 
 /* ---------------------------------------------------------------- matrices */
 
-/* CSR matrix (Section 2.2).  row_ptr: n+1 int32 (row_ptr[0] = 0,
+/* CSR matrix (Section 3.2).  row_ptr: n+1 int32 (row_ptr[0] = 0,
    nondecreasing, row_ptr[n] = nnz); col: nnz int32 in [0, n); val: nnz
    float64.  Rows are applied in stored order (store columns ascending).
    All three are device pointers, borrowed; col and val 16-byte aligned
@@ -139,7 +139,7 @@ its_status its_csr_set_lowp(its_matrix *A, const void *val_lo, int32_t dtype);
    then a pair and a single for the rest).  Every row keeps its stored entry order, so results are
    bit-identical to the unpacked matrix; the layout spares the row pointers
    and lets each wavefront read two entries of its 64 rows with one
-   coalesced access (the SpMV of Sections 2.1-2.2).  A slice whose rows have
+   coalesced access (the SpMV of Sections 3.1-3.2).  A slice whose rows have
    strictly ascending columns and take their column offsets (column - row)
    from one list as long as the slice width stores no column indices at
    all: one offset and one 64-lane mask per entry position replace them, and
@@ -191,7 +191,7 @@ int64_t its_csr_packed_slots(const its_matrix *A);
    every slice is an offset slice. */
 int64_t its_csr_packed_column_slots(const its_matrix *A);
 
-/* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 2.4:
+/* Point colouring for symmetric Gauss-Seidel on a CSR matrix (Section 3.4:
    colours, red-black without rotation).  color: n uint8 (device) with values
    < ncolors; each colour must be an independent set (no row couples to a
    row of its own colour) -- checked here, ITS_E_INVALID otherwise.  The
@@ -263,7 +263,7 @@ its_status its_workspace_size(const its_matrix *A, const its_options *opts, size
 /* Solves A x = b.  b: device, n.  x: device, n, in = x0, out = solution.
    Stops when ||r_k||_2 <= rtol ||b||_2 (the paper's test is absolute;
    Algorithms 1-2) or after max_iter iterations.  b = 0 returns x = 0.
-   Methods (Section 2.1):
+   Methods (Section 3.1):
      ITS_JACOBI   x_{k+1} = D^{-1}(b - (A - D) x_k), undamped;
      ITS_SGS      symmetric Gauss-Seidel: colours forward then backward;
      ITS_CG       classical CG (Hestenes-Stiefel), or mixed-precision IR;
@@ -297,7 +297,7 @@ const char *its_last_error(void); /* message of this thread's last error */
    its_varcoef_create), each with nrhs right-hand sides, solved by FP64 CG per
    (system, right-hand side) and advanced together.  The paper's experiments
    solve one large system per run; the batch is this library's analogue of
-   choosing the task granularity (Section 3.2): an autotuner picks how many
+   choosing the task granularity (Section 4.2): an autotuner picks how many
    z planes one brick of the SpMV pass covers, by timing that pass on the
    first solve.  Each (system, rhs) follows exactly the arithmetic of the
    single-system CG (the same iterates, bit for bit) and stops on its own

@@ -19,7 +19,7 @@
 /* alpha_n, alpha_d, beta, omega in Algorithms 1-2) are sums of products.  The */
 /* oracle returns the exact value of that sum rounded once to double, so the */
 /* result does not depend on summation order (the paper shows order-induced */
-/* rounding changes BiCGStab's convergence, Section 2.3).                     */
+/* rounding changes BiCGStab's convergence, Section 3.3).                     */
 /*                                                                           */
 /* Method: Shewchuk's non-overlapping expansions (Discrete Comput. Geom.     */
 /* 18, 1997): each new term is merged into a list of non-overlapping        */
@@ -84,7 +84,11 @@ static double acc_round(const orc_acc *a) {
     if (lo != 0.0) break;
   }
   /* hi is the round-to-nearest of hi+lo; if lo is exactly half an ulp the
-     remaining partials decide the direction of the tie. */
+     remaining partials decide the direction of the tie.  This final step
+     (sum the partials from the top, stop at the first inexact addition, then
+     correct a half-way case by the sign of the next partial) is the one of
+     CPython's math.fsum (Hettinger's msum recipe built on Shewchuk's
+     expansions). */
   if (n > 0 && ((lo < 0.0 && a->part[n - 1] < 0.0) || (lo > 0.0 && a->part[n - 1] > 0.0))) {
     double y = lo * 2.0;
     double x = hi + y;
@@ -119,8 +123,8 @@ double orc_dot_f32(int64_t n, const float *x, const float *y) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Sparse matrix-vector product on CSR (Section 2.2: HPCCG's CSR format;     */
-/* SpMV is the dominant kernel, Section 3.2).                                 */
+/* Sparse matrix-vector product on CSR (Section 3.2: HPCCG's CSR format;     */
+/* SpMV is the dominant kernel, Section 4.2).                                 */
 /* Reading: each row is a fused multiply-add chain over the stored entries,  */
 /* in stored (ascending column) order, starting from +0.                     */
 /* ------------------------------------------------------------------------ */
@@ -165,7 +169,7 @@ static double true_rel_res(int64_t n, const int64_t *rp, const int32_t *col, con
 
 /* Common start of every solver.  Reading of the stopping rule: the paper
    stops on the absolute test sqrt(alpha_n) < eps (Algorithms 1-2, Section
-   3.1); here the test is relative, ||r|| <= rtol*||b||, evaluated without a
+   4.1); here the test is relative, ||r|| <= rtol*||b||, evaluated without a
    square root as r.r <= thr2 with thr2 = (rtol*sqrt(b.b))^2.
    Returns 1 if the solve is already finished (invalid b, or b = 0, whose
    solution is x = 0). */
@@ -202,7 +206,7 @@ static int find_diag(int64_t n, const int64_t *rp, const int32_t *col, const dou
   return 0;
 }
 
-/* Relaxation update of row i (Section 2.1, Jacobi and Gauss-Seidel):
+/* Relaxation update of row i (Section 3.1, Jacobi and Gauss-Seidel):
    x_i <- (b_i - sum_{j != i} a_ij x_j) / a_ii.  Reading: the off-diagonal
    sum is the row's fma chain with the diagonal entry skipped, followed by one
    subtraction and one IEEE division. */
@@ -216,7 +220,7 @@ static double relax_row(const int64_t *rp, const int32_t *col, const double *val
 }
 
 /* ------------------------------------------------------------------------ */
-/* Jacobi (Section 2.1): x_{k+1} = D^{-1} (b - (A - D) x_k), undamped        */
+/* Jacobi (Section 3.1): x_{k+1} = D^{-1} (b - (A - D) x_k), undamped        */
 /* (Reading: the paper names no damping factor).  The residual of x_k is      */
 /* evaluated before each sweep; the result is the first x_k that passes.      */
 /* ------------------------------------------------------------------------ */
@@ -270,8 +274,8 @@ int orc_jacobi(int64_t n, const int64_t *rp, const int32_t *col, const double *v
 }
 
 /* ------------------------------------------------------------------------ */
-/* Symmetric Gauss-Seidel with a point colouring (Section 2.1: one forward    */
-/* sweep then one backward sweep per iteration; Section 2.4: colours, with   */
+/* Symmetric Gauss-Seidel with a point colouring (Section 3.1: one forward    */
+/* sweep then one backward sweep per iteration; Section 3.4: colours, with   */
 /* red-black and no rotation as the configuration used).                      */
 /* Reading: colours are point colours given by the caller and must be        */
 /* independent sets (no row couples to a row of its own colour).  The forward */
@@ -342,7 +346,7 @@ int orc_sgs(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
 
 /* ------------------------------------------------------------------------ */
 /* Conjugate gradient, classical Hestenes-Stiefel form (the CG that HPCCG    */
-/* applies, Section 2.2; the paper's notation alpha_n = r.r and              */
+/* applies, Section 3.2; the paper's notation alpha_n = r.r and              */
 /* alpha_d = (A p).p, Algorithm 1):                                           */
 /*   r0 = b - A x0, p0 = r0                                                   */
 /*   alpha = alpha_n / alpha_d, x += alpha p, r -= alpha A p,                 */
@@ -407,7 +411,7 @@ int orc_cg(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
 /* ------------------------------------------------------------------------ */
 /* CG-NB, the paper's nonblocking CG (Algorithm 1): the SpMV is applied to r  */
 /* and A p is carried by the recurrence A p_j = A r_j + beta_j A p_{j-1}, so   */
-/* the dot of r_j can overlap the SpMV (Section 2.1).                          */
+/* the dot of r_j can overlap the SpMV (Section 3.1).                          */
 /*   init: r0 = b - A x0, p0 = r0, (A p)0 = A r0, alpha_n = r0.r0,            */
 /*         alpha_d = (A p)0.p0, alpha = alpha_n / alpha_d                      */
 /*   j >= 1: r_j = r_{j-1} - alpha_{j-1} (A p)_{j-1}; alpha_n,j = r_j.r_j;     */
@@ -505,7 +509,7 @@ int orc_cgnb(int64_t n, const int64_t *rp, const int32_t *col, const double *val
 
 /* ------------------------------------------------------------------------ */
 /* BiCGStab with the operation list of Algorithm 2 (BiCGStab-B1), which is   */
-/* arithmetically the classical method (Section 2.1), including its restart.  */
+/* arithmetically the classical method (Section 3.1), including its restart.  */
 /*   init: r = b - A x, p = r, beta = r.r, r' = r/sqrt(beta), alpha_n = r.r'  */
 /*   loop: v = A p, alpha_d = v.r', alpha = alpha_n/alpha_d, s = r - alpha v, */
 /*         t = A s, omega = (t.s)/(t.t), x = (x + alpha p) + omega s,         */
@@ -627,7 +631,7 @@ int orc_bicgstab(int64_t n, const int64_t *rp, const int32_t *col, const double 
 
 /* ------------------------------------------------------------------------ */
 /* Mixed-precision iterative refinement around CG.  Not in the paper (it is  */
-/* FP64 throughout, Section 3.1); the outer loop is classical iterative      */
+/* FP64 throughout, Section 4.1); the outer loop is classical iterative      */
 /* refinement, the inner solve is the CG above on FP32 vectors.               */
 /*   outer (FP64): r = b - A x, test, rn = ||r||, rh = (float)(r/rn),         */
 /*                 inner solve A_lo d = rh, x = x + rn*d                      */

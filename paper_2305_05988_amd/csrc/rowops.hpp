@@ -3,7 +3,7 @@
 // with the vector entry x_j derived from what a fetch functor loads for
 // column j -- so a kernel can apply A to a vector it forms on the fly
 // (p = r + beta p, s = r - alpha v) without storing it first.  The SpMV of
-// the paper (Sections 2.1-2.2) is the chain with x_j = x[j].
+// the paper (Sections 3.1-3.2) is the chain with x_j = x[j].
 //
 // Tiles: kernels walk the rows in tiles of kBlock rows, one row per thread,
 // through tile_entries(r0, r1, smem, fetch, consume): for the thread's row it

@@ -1,4 +1,4 @@
-"""The paper's one-node iteration counts (Sec. 3.1: a 128 x 128 x 6144 grid,
+"""The paper's one-node iteration counts (Sec. 4.1: a 128 x 128 x 6144 grid,
 b = A 1, x0 = 0, stop when ||r||_2 < 1e-6, BiCGStab restart threshold 1e-5)
 reproduced under the reading that its matrix carries 27 on the diagonal and
 -1 on every neighbour, for the 7- and the 27-point stencil alike.

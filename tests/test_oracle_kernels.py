@@ -129,3 +129,32 @@ def test_spmv_f32_close_on_random():
     y = oracle.spmv_f32(A, A[2].astype(np.float32), x)
     ref = _scipy(A) @ x.astype(np.float64)
     assert np.max(np.abs(y - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+def test_spmv_f32_is_an_fp32_fma_chain_in_stored_order():
+    # Three rows whose FP32 chain differs from every plausible alternative:
+    #  row 0: [1, 1, 1] . [1, 2^-24, 2^-24].  In FP32 each 2^-24 is half an
+    #         ulp of 1 and rounds away (ties to even): exactly 1.  Summed in
+    #         double and rounded once it is 1 + 2^-23.
+    #  row 1: [a, -c] . [a, 1] with a = 1 + 2^-12, c = 1 + 2^-11: a*a is
+    #         1 + 2^-11 + 2^-24, whose FP32 rounding is c, so the fma chain
+    #         gives fma(-c, 1, round(a*a)) = 0; a product rounded before the
+    #         add, or the entries taken in reverse order
+    #         (fma(a, a, -c) = 2^-24), do not.
+    #  row 2: [-c, a] . [1, a]: the same entries stored the other way round,
+    #         whose chain is fma(a, a, -c) = 2^-24 exactly.
+    a = np.float32(1.0 + 2.0 ** -12)
+    c = np.float32(1.0 + 2.0 ** -11)
+    tiny = np.float32(2.0 ** -24)
+    # columns: 0 -> 1, 1 -> 2^-24, 2 -> 2^-24, 3 -> a, 4 -> 1
+    x = np.array([1.0, tiny, tiny, a, 1.0], np.float32)
+    rp = np.array([0, 3, 5, 7, 8, 9], np.int64)
+    col = np.array([0, 1, 2, 3, 4, 4, 3, 3, 4], np.int32)
+    val32 = np.array([1, 1, 1, a, -c, -c, a, 1, 1], np.float32)
+    A = (rp, col, val32.astype(np.float64))
+    y = oracle.spmv_f32(A, val32, x)
+    assert y.dtype == np.float32
+    assert y[0] == np.float32(1.0)
+    assert y[1] == np.float32(0.0)
+    assert y[2] == tiny
+    assert y[3] == a and y[4] == np.float32(1.0)

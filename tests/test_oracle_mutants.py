@@ -53,6 +53,18 @@ MUTANTS = [
     ("spmv reversed order", "for (k = rp[i]; k < rp[i + 1]; k++) acc = fma(val[k], x[col[k]], acc);",
      "for (k = rp[i + 1] - 1; k >= rp[i]; k--) acc = fma(val[k], x[col[k]], acc);",
      [K.test_spmv_is_an_fma_chain_in_stored_order]),
+    ("spmv_f32 accumulates in double",
+     "    float acc = 0.0f;\n    for (k = rp[i]; k < rp[i + 1]; k++) acc = fmaf(val[k], x[col[k]], acc);\n    y[i] = acc;",
+     "    double acc = 0.0;\n    for (k = rp[i]; k < rp[i + 1]; k++) acc = fma((double)val[k], (double)x[col[k]], acc);\n    y[i] = (float)acc;",
+     [K.test_spmv_f32_is_an_fp32_fma_chain_in_stored_order]),
+    ("spmv_f32 rounds each product",
+     "for (k = rp[i]; k < rp[i + 1]; k++) acc = fmaf(val[k], x[col[k]], acc);",
+     "for (k = rp[i]; k < rp[i + 1]; k++) acc = val[k] * x[col[k]] + acc;",
+     [K.test_spmv_f32_is_an_fp32_fma_chain_in_stored_order]),
+    ("spmv_f32 reversed order",
+     "for (k = rp[i]; k < rp[i + 1]; k++) acc = fmaf(val[k], x[col[k]], acc);",
+     "for (k = rp[i + 1] - 1; k >= rp[i]; k--) acc = fmaf(val[k], x[col[k]], acc);",
+     [K.test_spmv_f32_is_an_fp32_fma_chain_in_stored_order]),
     ("ir update unscaled", "x[i] = fma(rn, (double)d[i], x[i]);", "x[i] = x[i] + (double)d[i];",
      [lambda: S.test_ir_cg_reaches_fp64_accuracy(S.np.float32)]),
     ("varcoef face arithmetic mean", "return (2.0 * a * b) / (a + b);", "return 0.5 * (a + b);",
