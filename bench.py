@@ -65,6 +65,36 @@ def csr_bytes(n, nnz, val_bytes=8):
     return val_bytes * nnz + 4 * nnz + 4 * (n + 1)
 
 
+def packed_matrix_bytes(A, n):
+    """Bytes of the matrix representation one SpMV pass reads: for the packed
+    layout the padded value slots (8 B), the column indices of the slices
+    that keep them (4 B), the per-position offset (4 B) and lane mask (8 B)
+    of the offset slices and the int64 slice offsets -- no row pointers; for
+    an unpacked matrix the CSR arrays."""
+    slots, col_slots = A.packed_slots, A.packed_column_slots
+    if not slots:
+        return csr_bytes(n, A.nnz)
+    return (8 * slots + 4 * col_slots + 12 * ((slots - col_slots) // 64)
+            + 8 * ((n + 63) // 64 + 1))
+
+
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return model, avail
+
+
 def measured_traffic(sha):
     """HBM bytes per launch of the SpMV pass from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -80,23 +110,34 @@ def measured_traffic(sha):
 
 
 def cpu_baseline(steps_small=3, steps_large=13):
-    """The oracle's CG on the same 256^3 system, single-threaded, timed as the
-    difference of two runs so the per-iteration rate excludes setup."""
+    """The oracle's CG on the same 256^3 system, single-threaded and pinned to
+    one host core, timed as the difference of two runs so the per-iteration
+    rate excludes setup."""
     import oracle
     from paper_2305_05988_amd import inputs
+    model, avail = host_cpu()
     A = inputs.poisson7_csr(256)
     xs = inputs.uniform_vector(A[0].size - 1, 1)
     b = oracle.spmv(A, xs)
-    times = {}
-    for k in (steps_small, steps_large):
-        t0 = time.perf_counter()
-        oracle.cg(A, b, rtol=0.0, max_iter=k)
-        times[k] = time.perf_counter() - t0
+    saved = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    core = min(saved) if saved else None
+    if core is not None:
+        os.sched_setaffinity(0, {core})
+    try:
+        times = {}
+        for k in (steps_small, steps_large):
+            t0 = time.perf_counter()
+            oracle.cg(A, b, rtol=0.0, max_iter=k)
+            times[k] = time.perf_counter() - t0
+    finally:
+        if saved:
+            os.sched_setaffinity(0, saved)
     per_it = (times[steps_large] - times[steps_small]) / (steps_large - steps_small)
     return {"value": 1.0 / per_it, "unit": "iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps_large - steps_small} FP64 CG iterations of the 256^3 Poisson CSR "
                       f"system (difference of {steps_large}- and {steps_small}-iteration runs, "
-                      f"single thread)",
+                      f"single thread pinned to core {core})",
+            "host_cpu": model, "host_cores_available": avail, "pinned_core": core,
             "seconds": times[steps_small] + times[steps_large]}
 
 
@@ -162,20 +203,23 @@ def main():
     log(f"setup {N}^3 CSR n={n} nnz={nnz} layout {args.layout} (slots {slots}) in "
         f"{time.perf_counter() - t0:.1f}s")
 
-    M = csr_bytes(n, nnz)
     V = 8 * n
-    bytes_iter = M + 10 * V
-    bytes_pass1 = M + 3 * V  # read col, val, row_ptr, r and p (gathered); write q
-    # read r, p, q and write r, p every iteration; read and write x every
-    # other iteration (the x update is deferred by one iteration): 6V on average
-    bytes_pass2 = 6 * V
-    # bytes the packed layout itself moves in pass 1: padded value slots,
-    # column indices only in the slices that keep them, the per-position
-    # offset (4 B) and lane mask (8 B) of the offset slices, int64 slice
-    # offsets; no row pointers
+    # Bytes per launch and per iteration are those of the matrix
+    # representation the pass actually reads (packed layout: no row pointers,
+    # no columns in offset slices) plus the vector touches:
+    #   pass 1: matrix + gathered {r, p} pairs (2V) + q written (V);
+    #   pass 2: r, p, q read and r, p written every iteration, x read and
+    #           written every other iteration (its update is deferred by one
+    #           iteration): 6V on average.
+    # The CSR-equivalent figure (int32 columns and row pointers, as if the CSR
+    # arrays were streamed) is kept under its own keys.
+    M_csr = csr_bytes(n, nnz)
+    M = packed_matrix_bytes(A, n)
     col_slots = A.packed_column_slots
-    moved_pass1 = (8 * slots + 4 * col_slots + 12 * ((slots - col_slots) // 64)
-                   + 8 * ((n + 63) // 64 + 1) + 3 * V) if slots else bytes_pass1
+    bytes_pass1 = M + 3 * V
+    bytes_pass2 = 6 * V
+    bytes_iter = bytes_pass1 + bytes_pass2
+    csr_bytes_iter = M_csr + 10 * V
 
     opts = dict(method="cg", rtol=args.rtol, max_iter=20000)
     if args.fixed_iters:
@@ -208,10 +252,14 @@ def main():
             "achieved": bytes_pass1 / avg1 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": bytes_pass1 / avg1 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_pass1, "avg_launch_us": avg1 * 1e6,
-            "launches": l1, "kernel_src_sha": sha, "layout_bytes_per_launch": moved_pass1,
-            "layout_column_slots": col_slots, "layout_gbs": moved_pass1 / avg1 / 1e9,
+            "launches": l1, "kernel_src_sha": sha,
+            "layout_column_slots": col_slots, "layout_slots": slots,
+            "csr_equivalent_bytes_per_launch": M_csr + 3 * V,
+            "csr_equivalent_gbs": (M_csr + 3 * V) / avg1 / 1e9,
             "update_pass": {"kernel": "k_cg_pass2", "avg_launch_us": avg2 * 1e6,
-                            "achieved": bytes_pass2 / avg2 / 1e9}}
+                            "bytes_per_launch_avg": bytes_pass2,
+                            "achieved": bytes_pass2 / avg2 / 1e9,
+                            "frac": bytes_pass2 / avg2 / 1e9 / HBM_PEAK_GBS}}
     xerr = (x - xs).norm().item() / xs.norm().item()
     result = {
         "metric": METRIC, "value": its_per_s, "unit": "iters/s", "n_gpus": 1,
@@ -227,6 +275,8 @@ def main():
         "achieved_gbs": its_per_s * bytes_iter / 1e9,
         "hbm_frac": its_per_s * bytes_iter / 1e9 / HBM_PEAK_GBS,
         "algorithmic_bytes_per_iter": bytes_iter,
+        "csr_equivalent_bytes_per_iter": csr_bytes_iter,
+        "csr_equivalent_gbs": its_per_s * csr_bytes_iter / 1e9,
         "true_rel_res": info.true_rel_res, "rel_err_vs_xstar": xerr,
         "roofline": roof,
     }
@@ -492,21 +542,29 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     # the paper's CG-NB (Algorithm 1) on the same CSR system
     its.solve(A, b, method="cgnb", rtol=args.rtol, max_iter=20000)
     t, (xn, info) = timed(lambda: its.solve(A, b, method="cgnb", rtol=args.rtol, max_iter=20000))
+    Mp = packed_matrix_bytes(A, n)
+    # CG-NB: SpMV pass on r (matrix + {r, Ap} pairs gathered 2V + w written V),
+    # update pass (reads pairs 2V, p, w, x; writes pairs 2V, p, x): M + 12V
     ex["cgnb_256_csr"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t,
-                          "achieved_gbs": info.iters / t * (12 * nnz + 4 * (n + 1) + 12 * V) / 1e9,
+                          "bytes_per_iter": Mp + 12 * V,
+                          "achieved_gbs": info.iters / t * (Mp + 12 * V) / 1e9,
                           "true_rel_res": info.true_rel_res, "vs_cg_time": t / t64}
     # matrix-free stencil CG on the same grid
     S = its.StencilMatrix(N, N, N, inputs.POISSON7)
     its.solve(S, b, method="cg", rtol=args.rtol, max_iter=20000)
     t, (xs_, info) = timed(lambda: its.solve(S, b, method="cg", rtol=args.rtol, max_iter=20000))
+    # matrix-free: pass 1 gathers the {r, p} pairs (2V) and writes q (V);
+    # pass 2 moves 6V on average (x every other iteration): 9V
     ex["stencil_cg_256"] = {"iters": info.iters, "s": t, "iters_per_s": info.iters / t,
-                            "achieved_gbs": info.iters / t * 10 * V / 1e9}
+                            "bytes_per_iter": 9 * V,
+                            "achieved_gbs": info.iters / t * 9 * V / 1e9}
     # Jacobi: 2000 capped sweeps on the CSR system
     its.solve(A, b, method="jacobi", rtol=args.rtol, max_iter=50)
     t, (xj, info) = timed(lambda: its.solve(A, b, method="jacobi", rtol=args.rtol, max_iter=500))
-    M = 12 * nnz + 4 * (n + 1)
+    # the sweep reads the matrix, gathers x_k, reads b and writes x_{k+1}
     ex["jacobi_256_csr"] = {"sweeps": info.iters, "s": t, "sweeps_per_s": info.iters / t,
-                            "achieved_gbs": info.iters / t * (M + 3 * V) / 1e9}
+                            "bytes_per_sweep": Mp + 3 * V,
+                            "achieved_gbs": info.iters / t * (Mp + 3 * V) / 1e9}
     # red-black symmetric Gauss-Seidel, matrix-free
     its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=5)
     t, (xg, info) = timed(lambda: its.solve(S, b, method="sgs", rtol=args.rtol, max_iter=200))
@@ -534,11 +592,14 @@ def extras(its, inputs, A, b, xs, n, nnz, N, args, ws, s_per_it):
     reps = 10
     t, (xb, info) = timed(lambda: its.solve(C, b2, method="bicgstab", rtol=args.rtol, max_iter=2000),
                           reps=reps)
-    M2 = 12 * nnz2 + 4 * (n2 + 1)
+    # two SpMV passes over the matrix; the pair layout of the vectors moves
+    # 18V per iteration (one more than the fused minimum of 17V)
+    M2 = packed_matrix_bytes(C, n2)
     ex["bicgstab_192_convdiff_csr"] = {"iters": info.iters, "restarts": info.restarts,
                                        "s_per_solve": t, "iters_per_s": info.iters / t,
                                        "solves_per_s": 1.0 / t,
-                                       "achieved_gbs": info.iters / t * (2 * M2 + 17 * 8 * n2) / 1e9,
+                                       "bytes_per_iter": 2 * M2 + 18 * 8 * n2,
+                                       "achieved_gbs": info.iters / t * (2 * M2 + 18 * 8 * n2) / 1e9,
                                        "true_rel_res": info.true_rel_res}
     del C, x2, b2, xb
     ex["ir_27pt_192"] = ir_27pt(its, inputs, args)

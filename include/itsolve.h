@@ -118,6 +118,17 @@ void its_default_options(its_options *opts /* host, out */);
 its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                           const double *val, its_matrix **out /* host, out */);
 
+/* The same CSR matrix with 64-bit row pointers (Section 3.2's CSR, for
+   callers whose index type is int64).  row_ptr: n+1 int64, device; it is
+   narrowed on the device, at this call, into an int32 copy that the handle
+   owns (4 (n+1) bytes, freed by its_matrix_destroy), so row_ptr may be freed
+   afterwards.  col, val: as its_csr_create (borrowed).  Errors:
+   ITS_E_UNSUPPORTED when n or nnz is 2^31 or more; ITS_E_INVALID when a row
+   pointer lies outside [0, nnz] (the other structure checks are
+   its_csr_validate's).  Synchronises `stream`. */
+its_status its_csr_create64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, void *stream, its_matrix **out /* host, out */);
+
 /* Checks a CSR matrix on the device: row_ptr monotone and in range, columns
    in range and strictly ascending within each row.  If need_diag, every row
    must also hold a nonzero diagonal entry (Jacobi, Gauss-Seidel).
@@ -237,6 +248,14 @@ its_status its_varcoef_grad(const its_matrix *A, const double *x, const double *
 
 its_status its_matrix_destroy(its_matrix *A);
 int64_t its_matrix_rows(const its_matrix *A);
+
+/* Brick plan of a matrix-free operator's SpMV sweep (the 7- and 27-point
+   stencils of Section 3.1 and the variable-coefficient operator): plan (host,
+   4 int32, out) = x tiles of 64 points, y tiles of 4 points, z chunks, and
+   the z planes per chunk (the last chunk may hold fewer).  A block marches
+   one (x tile, y tile, z chunk) brick plane by plane.  Depends only on the
+   grid; ITS_E_INVALID for a CSR matrix. */
+its_status its_stencil_plan(const its_matrix *A, int32_t *plan);
 
 /* ----------------------------------------------------------------- kernels */
 

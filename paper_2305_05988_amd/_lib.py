@@ -19,13 +19,14 @@ MAX_KERNEL_CLASSES = 8
 
 # every symbol include/itsolve.h declares
 EXPORTS = (
-    "its_default_options", "its_csr_create", "its_csr_validate", "its_csr_set_lowp",
+    "its_default_options", "its_csr_create", "its_csr_create64", "its_csr_validate", "its_csr_set_lowp",
     "its_csr_set_colors", "its_stencil_create", "its_matrix_destroy", "its_matrix_rows",
     "its_spmv", "its_dot_workspace_size", "its_dot", "its_workspace_size", "its_solve",
     "its_cast_values", "its_stream_copy", "its_status_string", "its_last_error",
     "its_csr_pack", "its_csr_packed_slots", "its_csr_packed_column_slots", "its_varcoef_create", "its_varcoef_grad",
     "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
     "its_batch_solve", "its_batch_set_schedule", "its_csr_transpose", "its_csr_value_grad",
+    "its_stencil_plan",
 )
 
 
@@ -68,6 +69,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "its_default_options": (None, [P]),
         "its_csr_create": (st, [I64, I64, P, P, P, P]),
+        "its_csr_create64": (st, [I64, I64, P, P, P, P, P]),
         "its_csr_validate": (st, [P, I32, P]),
         "its_csr_set_lowp": (st, [P, P, I32]),
         "its_csr_pack": (st, [P, C.c_double, P]),
@@ -87,6 +89,7 @@ def load(path: str = LIB_PATH):
         "its_stencil_create": (st, [I32, I32, I32, I32, P, P]),
         "its_matrix_destroy": (st, [P]),
         "its_matrix_rows": (I64, [P]),
+        "its_stencil_plan": (st, [P, P]),
         "its_spmv": (st, [P, P, P, P]),
         "its_dot_workspace_size": (SZ, [I64]),
         "its_dot": (st, [I64, P, P, P, P, SZ, P]),

@@ -48,21 +48,37 @@ class _Matrix:
     def handle(self):
         return self._h
 
+    @property
+    def plan(self):
+        """Brick plan of a matrix-free operator's SpMV sweep: (x tiles, y
+        tiles, z chunks, planes per chunk)."""
+        p = (C.c_int32 * 4)()
+        L.check(L.lib().its_stencil_plan(self._h, p), "its_stencil_plan")
+        return tuple(int(v) for v in p)
+
 
 class CSRMatrix(_Matrix):
-    """CSR matrix on the GPU: int32 row_ptr (n+1), int32 col, float64 val.
-    The handle borrows the tensors; this object keeps them alive."""
+    """CSR matrix on the GPU: int32 or int64 row_ptr (n+1), int32 col,
+    float64 val.  The handle borrows col and val (and an int32 row_ptr; an
+    int64 one is narrowed by the library into a copy the handle owns); this
+    object keeps the tensors alive."""
 
     def __init__(self, row_ptr, col, val, val32=None, val16=None, validate=True):
         self.n = row_ptr.numel() - 1
         self.nnz = col.numel()
-        _vec(row_ptr, self.n + 1, "row_ptr", torch.int32)
+        if not isinstance(row_ptr, torch.Tensor) or row_ptr.dtype not in (torch.int32, torch.int64):
+            raise TypeError("row_ptr must be an int32 or int64 CUDA tensor")
+        _vec(row_ptr, self.n + 1, "row_ptr", row_ptr.dtype)
         _vec(col, self.nnz, "col", torch.int32)
         _vec(val, self.nnz, "val")
         self.row_ptr, self.col, self.val = row_ptr, col, val
         h = C.c_void_p()
-        L.check(L.lib().its_csr_create(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val),
-                                       C.byref(h)), "its_csr_create")
+        if row_ptr.dtype == torch.int64:
+            L.check(L.lib().its_csr_create64(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                             _stream(), C.byref(h)), "its_csr_create64")
+        else:
+            L.check(L.lib().its_csr_create(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                           C.byref(h)), "its_csr_create")
         self._h = h
         self.val32 = self.val16 = None
         if validate:
@@ -76,14 +92,14 @@ class CSRMatrix(_Matrix):
     @classmethod
     def from_numpy(cls, row_ptr, col, val, device="cuda", lowp=(), validate=True, pack=False,
                    max_fill=1.2):
-        """Uploads host CSR arrays (row_ptr narrowed to int32) and, for each
-        dtype name in ``lowp`` ("f32", "f16"), a low-precision copy of the
-        values made by the library's cast kernel; ``pack`` then builds the
-        library's packed device layout (its_csr_pack with ``max_fill``)."""
+        """Uploads host CSR arrays (an int64 row_ptr stays int64 and the
+        library narrows it) and, for each dtype name in ``lowp`` ("f32",
+        "f16"), a low-precision copy of the values made by the library's cast
+        kernel; ``pack`` then builds the library's packed device layout
+        (its_csr_pack with ``max_fill``)."""
         rp = np.asarray(row_ptr)
-        if rp[-1] >= 2 ** 31:
-            raise ValueError("nnz must be below 2^31")
-        t_rp = torch.from_numpy(np.ascontiguousarray(rp, dtype=np.int32)).to(device)
+        rdt = np.int64 if rp.dtype == np.int64 else np.int32
+        t_rp = torch.from_numpy(np.ascontiguousarray(rp, dtype=rdt)).to(device)
         t_col = torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device)
         t_val = torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(device)
         A = cls(t_rp, t_col, t_val, validate=validate)

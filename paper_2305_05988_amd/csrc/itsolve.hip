@@ -999,6 +999,48 @@ its_status its_csr_create(int64_t n, int64_t nnz, const int32_t *row_ptr, const 
   return ITS_OK;
 }
 
+its_status its_csr_create64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                            const double *val, void *stream, its_matrix **out) {
+  if (!out) return fail(ITS_E_INVALID, "out is null");
+  *out = nullptr;
+  if (n < 0 || nnz < 0) return fail(ITS_E_INVALID, "negative size");
+  if (n >= (int64_t(1) << 31) - 1 || nnz >= (int64_t(1) << 31))
+    return fail(ITS_E_UNSUPPORTED, "n and nnz must be below 2^31 to narrow the row pointers");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(ITS_E_INVALID, "null CSR array");
+  if ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(val)) % 16)
+    return fail(ITS_E_INVALID, "col and val must be 16-byte aligned");
+  int32_t *rp32 = nullptr;
+  uint32_t *bad = nullptr;
+  HIP_TRY(hipMalloc(&rp32, sizeof(int32_t) * size_t(n + 1)));
+  if (hipMalloc(&bad, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(rp32);
+    return fail(ITS_E_HIP, "device allocation failed");
+  }
+  hipStream_t s = S(stream);
+  uint32_t hbad = 0;
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(uint32_t), s);
+  if (e == hipSuccess) {
+    const int grid = int(std::min<int64_t>((n + 1 + kBlock - 1) / kBlock, 65536));
+    hipLaunchKernelGGL(k_narrow_rp, dim3(grid), dim3(kBlock), 0, s, n + 1, nnz, row_ptr, rp32, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(bad);
+  if (e != hipSuccess || hbad) {
+    (void)hipFree(rp32);
+    if (e != hipSuccess) return fail(ITS_E_HIP, std::string("narrowing row pointers: ") + hipGetErrorString(e));
+    return fail(ITS_E_INVALID, std::to_string(hbad) + " row pointers outside [0, nnz]");
+  }
+  its_status st = its_csr_create(n, nnz, rp32, col, val, out);
+  if (st != ITS_OK) {
+    (void)hipFree(rp32);
+    return st;
+  }
+  (*out)->own_rp = rp32;  // freed by its_matrix_destroy
+  return ITS_OK;
+}
+
 its_status its_stencil_create(int32_t nx, int32_t ny, int32_t nz, int32_t npts, const double *coef,
                               its_matrix **out) {
   if (!out) return fail(ITS_E_INVALID, "out is null");
@@ -1040,6 +1082,24 @@ its_status its_matrix_destroy(its_matrix *A) {
 }
 
 int64_t its_matrix_rows(const its_matrix *A) { return A ? A->n : -1; }
+
+its_status its_stencil_plan(const its_matrix *A, int32_t *plan) {
+  if (!A || !plan) return fail(ITS_E_INVALID, "null argument");
+  if (A->kind == kCsr) return fail(ITS_E_INVALID, "not a matrix-free operator");
+  return with_op64(A, [&](auto op) -> its_status {
+    if constexpr (std::is_same_v<decltype(op), VarCoefOp> ||
+                  std::is_same_v<decltype(op), StencilOp<7, double>> ||
+                  std::is_same_v<decltype(op), StencilOp<27, double>>) {
+      plan[0] = op.nbx;
+      plan[1] = op.nby;
+      plan[2] = op.nbz;
+      plan[3] = op.zb;
+      return ITS_OK;
+    } else {
+      return fail(ITS_E_INVALID, "not a matrix-free operator");
+    }
+  });
+}
 
 its_status its_varcoef_create(int32_t nx, int32_t ny, int32_t nz, const double *k,
                               its_matrix **out) {
@@ -1493,8 +1553,24 @@ its_status its_workspace_size(const its_matrix *A, const its_options *o, size_t 
   return ITS_OK;
 }
 
+}  // extern "C"
+
+static its_status solve_impl(const its_matrix *Ac, const its_options *o, const double *b, double *x,
+                             void *workspace, size_t ws_bytes, void *stream, its_result *res,
+                             bool cache_graph);
+
+extern "C" {
+
 its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b, double *x,
                      void *workspace, size_t ws_bytes, void *stream, its_result *res) {
+  return solve_impl(Ac, o, b, x, workspace, ws_bytes, stream, res, true);
+}
+
+}  // extern "C"
+
+static its_status solve_impl(const its_matrix *Ac, const its_options *o, const double *b, double *x,
+                             void *workspace, size_t ws_bytes, void *stream, its_result *res,
+                             bool cache_graph) {
   its_matrix *A = const_cast<its_matrix *>(Ac);  // only cached validation state changes
   if (!A || !o || !res) return fail(ITS_E_INVALID, "null argument");
   // A^T: a constant stencil with its offsets reflected (entry (i, i+d) of A^T
@@ -1543,8 +1619,8 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
   // the iteration loops run as a cached HIP graph (eagerly when profiling);
   // the key lists what the captured launches depend on
   its_matrix *owner = const_cast<its_matrix *>(Ac);
-  run.gc = o->graph == 1 ? &owner->graph : nullptr;
-  {
+  run.gc = (o->graph == 1 && cache_graph) ? &owner->graph : nullptr;
+  if (run.gc) {
     uint64_t rt;
     std::memcpy(&rt, &o->restart_tol, sizeof(rt));
     run.key = {uint64_t(o->method), uint64_t(o->inner_dtype), uint64_t(o->restart_mode), rt,
@@ -1580,6 +1656,8 @@ its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b
   if (s != ITS_OK) return s;
   return static_cast<its_status>(res->status);
 }
+
+extern "C" {
 
 its_status its_cast_values(const double *src, void *dst, int32_t dtype, int64_t count, void *stream) {
   if (count < 0) return fail(ITS_E_INVALID, "negative count");

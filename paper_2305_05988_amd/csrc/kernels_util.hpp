@@ -32,6 +32,20 @@ __global__ void __launch_bounds__(kBlock) k_copy(int64_t n, const double *__rest
   if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
 }
 
+// 64-bit row pointers narrowed to 32 bits: dst[i] = src[i] for i < count,
+// counting into *bad the pointers outside [0, nnz] (their copy is
+// meaningless and the caller refuses the matrix).
+__global__ void __launch_bounds__(kBlock) k_narrow_rp(int64_t count, int64_t nnz,
+                                                      const int64_t *__restrict__ src,
+                                                      int32_t *__restrict__ dst, uint32_t *bad) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t v = src[i];
+    const bool ok = v >= 0 && v <= nnz;
+    dst[i] = ok ? int32_t(v) : 0;
+    if (!ok) atomicAdd(bad, 1u);
+  }
+}
+
 // CSR structure check: counts bad rows into *bad.
 __global__ void __launch_bounds__(kBlock) k_csr_check(int32_t n, int32_t nnz,
                                                       const int32_t *__restrict__ rp,

@@ -58,6 +58,15 @@ def test_host_side_argument_errors(lib):
     assert lib.its_csr_create(-1, 0, P0, P0, P0, C.byref(h)) == L.ITS_E_INVALID
     assert lib.its_csr_create(1 << 31, 1, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
                               C.byref(h)) == L.ITS_E_UNSUPPORTED
+    assert lib.its_csr_create64(4, 4, P0, P0, P0, P0, C.byref(h)) == L.ITS_E_INVALID
+    assert lib.its_csr_create64(4, -1, C.c_void_p(8), C.c_void_p(16), C.c_void_p(16), P0,
+                                C.byref(h)) == L.ITS_E_INVALID
+    assert lib.its_csr_create64(8, 1 << 31, C.c_void_p(8), C.c_void_p(16), C.c_void_p(16), P0,
+                                C.byref(h)) == L.ITS_E_UNSUPPORTED
+    assert lib.its_csr_create64(4, 4, C.c_void_p(8), C.c_void_p(8), C.c_void_p(16), P0,
+                                C.byref(h)) == L.ITS_E_INVALID  # col not 16-byte aligned
+    assert lib.its_csr_create64(4, 4, C.c_void_p(8), C.c_void_p(16), C.c_void_p(16), P0,
+                                P0) == L.ITS_E_INVALID
     coef = (C.c_double * 7)(*([1.0] * 7))
     assert lib.its_stencil_create(4, 4, 4, 5, coef, C.byref(h)) == L.ITS_E_INVALID
     assert lib.its_stencil_create(2048, 2048, 1024, 7, coef, C.byref(h)) == L.ITS_E_UNSUPPORTED
@@ -87,3 +96,5 @@ def test_host_side_argument_errors(lib):
     assert lib.its_batch_destroy(P0) == L.ITS_OK
     assert lib.its_csr_packed_slots(P0) == 0
     assert lib.its_csr_packed_column_slots(P0) == 0
+    plan = (C.c_int32 * 4)()
+    assert lib.its_stencil_plan(P0, plan) == L.ITS_E_INVALID

@@ -96,6 +96,41 @@ def test_spmv_bit_exact_csr_and_stencil(g, kind):
     assert np.array_equal(host(its().spmv(S, dev(x))), ref)
 
 
+def test_csr_int64_row_pointers_narrowed_on_device():
+    import ctypes as C
+    from paper_2305_05988_amd import _lib as L
+    rp, col, val = inputs.poisson7_csr(17, 9, 5)
+    assert rp.dtype == np.int64
+    n, nnz = rp.size - 1, col.size
+    x = inputs.uniform_vector(n, 3)
+    ref = oracle.spmv((rp, col, val), x)
+    t_col, t_val = dev(col), dev(val)
+    t_rp64 = dev(rp)
+    h = C.c_void_p()
+    lib = L.lib()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.its_csr_create64(n, nnz, C.c_void_p(t_rp64.data_ptr()), C.c_void_p(t_col.data_ptr()),
+                                C.c_void_p(t_val.data_ptr()), s, C.byref(h)) == L.ITS_OK
+    del t_rp64  # the handle holds its own narrowed copy
+    torch.cuda.synchronize()
+    try:
+        assert lib.its_csr_validate(h, 1, s) == L.ITS_OK
+        xd, yd = dev(x), torch.empty(n, dtype=torch.float64, device="cuda")
+        assert lib.its_spmv(h, C.c_void_p(xd.data_ptr()), C.c_void_p(yd.data_ptr()), s) == L.ITS_OK
+        assert np.array_equal(host(yd), ref)
+    finally:
+        lib.its_matrix_destroy(h)
+    # through the binding, packed, and a row pointer out of range refused
+    A = its().CSRMatrix(dev(rp), t_col, t_val)
+    A.pack(max_fill=2.0)
+    assert np.array_equal(host(its().spmv(A, dev(x))), ref)
+    bad = rp.copy()
+    bad[3] = nnz + 1
+    with pytest.raises(its().ItsError) as e:
+        its().CSRMatrix(dev(bad), t_col, t_val)
+    assert e.value.status == L.ITS_E_INVALID
+
+
 def test_spmv_empty_and_ragged_rows():
     # rows 1 and 3 empty, ragged lengths
     rp = np.array([0, 3, 3, 4, 4, 7], np.int64)
