@@ -298,6 +298,27 @@ its_status its_workspace_size(const its_matrix *A, const its_options *opts, size
 its_status its_solve(const its_matrix *A, const its_options *opts, const double *b, double *x,
                      void *workspace, size_t ws_bytes, void *stream, its_result *res);
 
+/* Bytes of the static device scratch of its_solve_noalloc (per device). */
+#define ITS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* its_solve for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same solve, bit for bit, with its workspace (the device State blocks, the
+   reduction partials and the method's vectors, its_workspace_size bytes) in
+   a static device array of ITS_NOALLOC_SCRATCH_BYTES that the library holds
+   on every device it runs on until the process ends.  No device memory is
+   allocated or freed by this call.  Limits: its_workspace_size for the
+   matrix and options must not exceed ITS_NOALLOC_SCRATCH_BYTES
+   (ITS_E_WORKSPACE otherwise: for FP64 CG about 2.7M rows, BiCGStab 1.1M,
+   Jacobi 8M); opts->graph and opts->profile must be 0 (ITS_E_UNSUPPORTED:
+   both would create HIP objects).  Every call on one device shares that
+   device's array, so calls that overlap on one device (concurrent streams
+   or threads) race and must be serialised by the caller; each call
+   initialises the scratch it reads, so nothing carries over between calls.
+   Other arguments, results and errors as its_solve. */
+its_status its_solve_noalloc(const its_matrix *A, const its_options *opts, const double *b, double *x,
+                             void *stream, its_result *res);
+
 /* --------------------------------------------------------------- utilities */
 
 /* dst[i] = src[i] rounded to nearest-even in dtype (ITS_F32 or ITS_F16):

@@ -7,6 +7,6 @@ in the HIP library libitsolve.so (C ABI in
 include/itsolve.h); this package only marshals torch tensors to it.
 """
 from .api import (Batch, CSRMatrix, SolveInfo, StencilMatrix, VarCoefMatrix, cast_values,  # noqa: F401
-                  csr_solve, diffusion_solve, dot, solve, spmv, stencil_solve,
+                  csr_solve, diffusion_solve, dot, solve, solve_noalloc, spmv, stencil_solve,
                   stream_copy, varcoef_grad)
 from ._lib import ItsError  # noqa: F401

@@ -16,6 +16,7 @@ ITS_JACOBI, ITS_SGS, ITS_CG, ITS_BICGSTAB, ITS_CG_NB = 0, 1, 2, 3, 4
 ITS_F64, ITS_F32, ITS_F16 = 0, 1, 2
 ITS_RESTART_COSINE, ITS_RESTART_PAPER = 0, 1
 MAX_KERNEL_CLASSES = 8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ITS_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/itsolve.h declares
 EXPORTS = (
@@ -26,7 +27,7 @@ EXPORTS = (
     "its_csr_pack", "its_csr_packed_slots", "its_csr_packed_column_slots", "its_varcoef_create", "its_varcoef_grad",
     "its_batch_create", "its_batch_destroy", "its_batch_cells", "its_batch_workspace_size",
     "its_batch_solve", "its_batch_set_schedule", "its_csr_transpose", "its_csr_value_grad",
-    "its_stencil_plan",
+    "its_stencil_plan", "its_solve_noalloc",
 )
 
 
@@ -95,6 +96,7 @@ def load(path: str = LIB_PATH):
         "its_dot": (st, [I64, P, P, P, P, SZ, P]),
         "its_workspace_size": (st, [P, P, P]),
         "its_solve": (st, [P, P, P, P, P, SZ, P, P]),
+        "its_solve_noalloc": (st, [P, P, P, P, P, P]),
         "its_cast_values": (st, [P, P, I32, I64, P]),
         "its_stream_copy": (st, [P, P, I64, P]),
         "its_status_string": (C.c_char_p, [I32]),

@@ -289,6 +289,20 @@ def solve(A, b, x0=None, workspace=None, **opts):
     return x, info
 
 
+def solve_noalloc(A, b, x, **opts):
+    """Solves A x = b in place of x (holding x0) with its_solve_noalloc: the
+    workspace is the library's static device scratch, so this call allocates
+    no device memory (b and x are the caller's).  Returns SolveInfo."""
+    b = _vec(b, A.n, "b")
+    x = _vec(x, A.n, "x")
+    o = options(**opts)
+    r = L.Result()
+    st = L.check(L.lib().its_solve_noalloc(A.handle, C.byref(o), _ptr(b), _ptr(x), _stream(),
+                                           C.byref(r)), "its_solve_noalloc")
+    return SolveInfo(_STATUS.get(st, str(st)), st, r.iters, r.inner_iters, r.restarts,
+                     r.rel_res, r.true_rel_res, list(r.kernel_ms), list(r.kernel_launches))
+
+
 class _DiffusionSolve(torch.autograd.Function):
     """x = A(k)^{-1} b for the variable-coefficient diffusion operator.
     Backward: one adjoint solve A lam = dL/dx (A is symmetric), then

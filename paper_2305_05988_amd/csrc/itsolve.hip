@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 #include <cstdio>
@@ -1555,6 +1556,37 @@ its_status its_workspace_size(const its_matrix *A, const its_options *o, size_t 
 
 }  // extern "C"
 
+// ------------------------------------------------------------ static scratch
+// The workspace of its_solve_noalloc: one array per device in the code
+// object's device memory, for callers that cannot allocate.  Its device
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is used by the host; the array's name here
+// is a host-side stand-in.
+namespace {
+constexpr size_t kScratchBytes = ITS_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+its_status scratch_for_current_device(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ITS_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ITS_E_HIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ITS_OK;
+}
+}  // namespace
+
+// The body of its_solve and its_solve_noalloc.  cache_graph: the iteration
+// loop may run as the handle's cached HIP graph (its_options.graph).
 static its_status solve_impl(const its_matrix *Ac, const its_options *o, const double *b, double *x,
                              void *workspace, size_t ws_bytes, void *stream, its_result *res,
                              bool cache_graph);
@@ -1564,6 +1596,24 @@ extern "C" {
 its_status its_solve(const its_matrix *Ac, const its_options *o, const double *b, double *x,
                      void *workspace, size_t ws_bytes, void *stream, its_result *res) {
   return solve_impl(Ac, o, b, x, workspace, ws_bytes, stream, res, true);
+}
+
+its_status its_solve_noalloc(const its_matrix *A, const its_options *o, const double *b, double *x,
+                             void *stream, its_result *res) {
+  if (!A || !o || !res) return fail(ITS_E_INVALID, "null argument");
+  std::string why;
+  if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
+  if (o->graph != 0) return fail(ITS_E_UNSUPPORTED, "its_solve_noalloc does not capture graphs (graph must be 0)");
+  if (o->profile != 0) return fail(ITS_E_UNSUPPORTED, "its_solve_noalloc does not profile (profile must be 0)");
+  const size_t need = layout_for(A->n, o->method, o->inner_dtype).total;
+  if (need > kScratchBytes)
+    return fail(ITS_E_WORKSPACE, "its_solve_noalloc: this solve needs " + std::to_string(need) +
+                                     " bytes of scratch; the static buffer holds " +
+                                     std::to_string(kScratchBytes) + " (use its_solve with a workspace)");
+  void *ws = nullptr;
+  its_status st = scratch_for_current_device(&ws);
+  if (st != ITS_OK) return st;
+  return solve_impl(A, o, b, x, ws, kScratchBytes, stream, res, false);
 }
 
 }  // extern "C"
