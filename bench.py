@@ -157,8 +157,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
     ap.add_argument("--extra-only",
-                    choices=("batched", "small32", "differentiation", "paper_counts"),
-                    help="profiling: run only this secondary workload and print its figures")
+                    choices=("batched", "small32", "differentiation", "paper_counts", "kernels"),
+                    help="profiling: run only this secondary workload and print its figures "
+                         "(kernels: a few fixed iterations of every benchmark workload, one "
+                         "after the other, with each kernel's bytes per launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
@@ -184,7 +186,7 @@ def main():
         del src, dst
     if args.extra_only:
         fn = {"batched": batched, "small32": small32, "differentiation": differentiation,
-              "paper_counts": paper_counts}
+              "paper_counts": paper_counts, "kernels": kernel_suite}
         print(json.dumps({args.extra_only: fn[args.extra_only](its, inputs)}), flush=True)
         return
     N = args.n
@@ -358,18 +360,38 @@ def small32(its, inputs, N=32):
     A.set_colors(inputs.redblack_colors(N, N, N), 2)
     b = its.spmv(A, torch.from_numpy(inputs.uniform_vector(n, 1)).cuda())
     out = {}
+
+    def med(kw, env=None):
+        saved = {k: os.environ.get(k) for k in (env or {})}
+        os.environ.update(env or {})
+        try:
+            its.solve(A, b, rtol=1e-8, **kw)
+            ts = []
+            for _ in range(5):
+                t, (x, info) = timed(lambda: its.solve(A, b, rtol=1e-8, **kw))
+                ts.append(t)
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        t = statistics.median(ts)
+        return {"iters": info.iters, "status": info.status, "s": t, "iters_per_s": info.iters / t}
+
     for method, cap in (("cg", 5000), ("bicgstab", 5000), ("cgnb", 5000), ("jacobi", 2000),
                         ("sgs", 5000)):
         for graph in (False, True):
-            its.solve(A, b, method=method, rtol=1e-8, max_iter=cap, graph=graph)
-            ts = []
-            for _ in range(5):
-                t, (x, info) = timed(lambda: its.solve(A, b, method=method, rtol=1e-8,
-                                                       max_iter=cap, graph=graph))
-                ts.append(t)
-            t = statistics.median(ts)
-            out[method + ("_graph" if graph else "")] = {
-                "iters": info.iters, "status": info.status, "s": t, "iters_per_s": info.iters / t}
+            out[method + ("_graph" if graph else "")] = med(dict(method=method, max_iter=cap,
+                                                                 graph=graph))
+    # one persistent cooperative kernel per solve (grid barriers); BiCGStab
+    # with B1's split-phase barriers and, for comparison, with all three
+    # barriers blocking
+    for method in ("cg", "cgnb", "bicgstab"):
+        out[method + "_persistent"] = med(dict(method=method, max_iter=5000, persistent=True))
+    out["bicgstab_persistent_blocking"] = med(dict(method="bicgstab", max_iter=5000,
+                                                   persistent=True),
+                                              env={"ITS_BICGSTAB_SPLIT": "0"})
     log(f"32^3: {json.dumps(out)}")
     return out
 
@@ -516,6 +538,96 @@ def paper_counts(its, inputs, grid=(128, 128, 6144)):
         out[f"{npts}pt_diag{diag:g}"] = row
         del S, b
         torch.cuda.empty_cache()
+    return out
+
+
+def kernel_suite(its, inputs, iters=10):
+    """A few fixed iterations of each benchmark workload, one after the other
+    in one process, for per-kernel profiles (rocprofv3 kernel trace and HBM
+    counters): for every workload the bytes per launch each of its kernels
+    needs -- the matrix representation it reads (packed layout: no row
+    pointers, no columns in offset slices) plus its vector touches.  V = 8n,
+    V32 = 4n.  Kernels shared by two workloads of different sizes are told
+    apart by their grid."""
+    import torch
+    out = {}
+
+    def run(A, b, **kw):
+        its.solve(A, b, **kw)
+        torch.cuda.synchronize()
+
+    def packed_lowp_bytes(A, n, vb):
+        slots, cs = A.packed_slots, A.packed_column_slots
+        return vb * slots + 4 * cs + 12 * ((slots - cs) // 64) + 8 * ((n + 63) // 64 + 1)
+
+    # 256^3 Poisson, packed CSR with FP32 and FP16 value copies
+    N = 256
+    rp, col, val = inputs.poisson7_csr(N)
+    n = rp.size - 1
+    A = its.CSRMatrix.from_numpy(rp, col, val, lowp=("f32", "f16"), validate=False, pack=True)
+    del rp, col, val
+    b = its.spmv(A, torch.from_numpy(inputs.uniform_vector(n, 1)).cuda())
+    V, V32 = 8 * n, 4 * n
+    M, M32, M16 = packed_matrix_bytes(A, n), packed_lowp_bytes(A, n, 4), packed_lowp_bytes(A, n, 2)
+    log(f"kernels: cg 256^3 ({iters} iterations)")
+    run(A, b, method="cg", rtol=0.0, max_iter=iters)
+    log(f"kernels: jacobi 256^3 ({iters} sweeps)")
+    run(A, b, method="jacobi", rtol=0.0, max_iter=iters)
+    for lowp, Ml in (("f32", M32), ("f16", M16)):
+        log(f"kernels: refinement ({lowp} values) 256^3 ({iters} inner iterations)")
+        run(A, b, method="cg", rtol=1e-12, max_iter=iters, inner_dtype=lowp, inner_rtol=1e-30)
+    out["poisson256_packed"] = {
+        "n": n, "grid_spmv": (n + 255) // 256,
+        "k_cg_pass1<SellOp<double": M + 3 * V, "k_cg_pass2<double>": 6 * V,
+        "k_jacobi<SellOp<double": M + 3 * V,
+        "k_cg_pass1<SellOp<float": M32 + 3 * V32, "k_cg_pass1<SellOp<__half": M16 + 3 * V32,
+        "k_cg_pass2_f32x2": 6 * V32, "k_residual<SellOp<double": M + 3 * V}
+    del A, b
+    torch.cuda.empty_cache()
+    # 256^3 matrix-free 7-point stencil
+    S = its.StencilMatrix(N, N, N, inputs.POISSON7)
+    b = torch.from_numpy(inputs.uniform_vector(n, 1)).cuda()
+    log(f"kernels: matrix-free cg 256^3 ({iters} iterations)")
+    run(S, b, method="cg", rtol=0.0, max_iter=iters)
+    log(f"kernels: matrix-free red-black sgs 256^3 ({iters} iterations)")
+    run(S, b, method="sgs", rtol=0.0, max_iter=iters)
+    out["poisson256_stencil"] = {"n": n, "k_cg_pass1<StencilOp<7, double": 3 * V,
+                                 "k_gs_stencil<7>": 3 * V // 2 + V // 2,
+                                 "k_gs_check<StencilOp<7, double": 2 * V}
+    del S, b
+    torch.cuda.empty_cache()
+    # 192^3 upwind convection-diffusion, packed CSR
+    rp, col, val = inputs.convdiff7_csr(192)
+    n2 = rp.size - 1
+    C2 = its.CSRMatrix.from_numpy(rp, col, val, validate=False, pack=True)
+    del rp, col, val
+    b2 = its.spmv(C2, torch.from_numpy(inputs.uniform_vector(n2, 1)).cuda())
+    log(f"kernels: bicgstab 192^3 upwind ({iters} iterations)")
+    run(C2, b2, method="bicgstab", rtol=0.0, max_iter=iters)
+    M2, V2 = packed_matrix_bytes(C2, n2), 8 * n2
+    out["convdiff192_packed"] = {"n": n2, "k_bicg_a<": M2 + 6 * V2, "k_bicg_b<": M2 + 3 * V2,
+                                 "k_bicg_c": 9 * V2}
+    del C2, b2
+    torch.cuda.empty_cache()
+    # 192^3 27-point, packed CSR with FP32 and FP16 value copies
+    rp, col, val = inputs.stencil27_csr(192)
+    A3 = its.CSRMatrix.from_numpy(rp, col, val, lowp=("f32", "f16"), validate=False, pack=True)
+    del rp, col, val
+    b3 = its.spmv(A3, torch.from_numpy(inputs.uniform_vector(n2, 1)).cuda())
+    log(f"kernels: cg 27-point 192^3 ({iters} iterations)")
+    run(A3, b3, method="cg", rtol=0.0, max_iter=iters)
+    for lowp in ("f32", "f16"):
+        log(f"kernels: refinement ({lowp} values) 27-point 192^3 ({iters} inner iterations)")
+        run(A3, b3, method="cg", rtol=1e-12, max_iter=iters, inner_dtype=lowp, inner_rtol=1e-30)
+    V3, V3_32 = 8 * n2, 4 * n2
+    out["stencil27_192_packed"] = {
+        "n": n2, "k_cg_pass1<SellOp<double": packed_matrix_bytes(A3, n2) + 3 * V3,
+        "k_cg_pass2<double>": 6 * V3,
+        "k_cg_pass1<SellOp<float": packed_lowp_bytes(A3, n2, 4) + 3 * V3_32,
+        "k_cg_pass1<SellOp<__half": packed_lowp_bytes(A3, n2, 2) + 3 * V3_32,
+        "k_cg_pass2_f32x2": 6 * V3_32}
+    del A3, b3
+    torch.cuda.empty_cache()
     return out
 
 

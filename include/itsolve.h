@@ -80,7 +80,18 @@ typedef struct {
                            on a stream the handle owns, then replayed; results
                            are identical to launch-by-launch).  Not with
                            profile.  0 (default): launch kernel by kernel */
-  int32_t pad;
+  int32_t persistent;   /* CG (FP64), CG-NB and BiCGStab only (else
+                           ITS_E_UNSUPPORTED).  1: the whole iteration loop
+                           runs as one cooperative kernel whose co-resident
+                           blocks meet at grid barriers, for small systems
+                           whose iterations are bound by launch and reduction
+                           latency; the reductions CG-NB and BiCGStab-B1 do
+                           not wait for (Algorithms 1-2) overlap the SpMV or
+                           an x update.  Same iterates bit for bit.  A barrier
+                           wait is bounded (environment ITS_BARRIER_SPIN_LIMIT
+                           polls, default 2^24); a wait that runs out ends
+                           every block and the solve returns ITS_E_HIP.  0
+                           (default): one kernel per pass */
 } its_options;
 
 #define ITS_MAX_KERNEL_CLASSES 8

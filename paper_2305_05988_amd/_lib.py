@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("inner_dtype", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int64),
                 ("profile", C.c_int32), ("transpose", C.c_int32),
-                ("graph", C.c_int32), ("pad", C.c_int32)]
+                ("graph", C.c_int32), ("persistent", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -244,7 +244,7 @@ class SolveInfo:
 
 def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mode="cosine",
             inner_dtype="f64", inner_rtol=1e-4, max_outer=30, check_every=0, profile=False,
-            transpose=False, graph=False):
+            transpose=False, graph=False, persistent=False):
     o = L.Options()
     L.lib().its_default_options(C.byref(o))
     o.method = _METHODS[method]
@@ -259,6 +259,7 @@ def options(method="cg", rtol=1e-8, max_iter=10000, restart_tol=1e-5, restart_mo
     o.profile = int(profile)
     o.transpose = int(bool(transpose))
     o.graph = int(bool(graph))
+    o.persistent = int(bool(persistent))
     return o
 
 

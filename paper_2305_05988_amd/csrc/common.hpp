@@ -246,15 +246,11 @@ __global__ void __launch_bounds__(kBlock) k_finish_group(Reduce *R, int G) {
   }
 }
 
-// Single block: reduce `count` partials (from p1 if `level` is 1, else p2;
-// thread t adds partials t, t + kBlock, ... in that order) and apply Fin
-// (the pass's scalar update) to the totals.
+// One block reduces `count` partials src[d][0 .. count) (thread t adds
+// partials t, t + kBlock, ... in that order), then thread 0 applies Fin (the
+// pass's scalar update) to the totals.  Every thread of the block calls it.
 template <int ND, class Fin>
-__global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, int level, Fin fin) {
-  if (!fin.active()) return;
-  const DD *src[ND];
-#pragma unroll
-  for (int d = 0; d < ND; ++d) src[d] = level == 1 ? R->p1[d] : R->p2[d];
+__device__ __forceinline__ void finish_in_block(const DD *const (&src)[ND], int count, Fin fin) {
   DD v[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) v[d] = DD{0.0, 0.0};
@@ -277,8 +273,176 @@ __global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, i
   if (threadIdx.x == 0) fin(v);
 }
 
+// Single block: reduce `count` partials (from p1 if `level` is 1, else p2)
+// and apply Fin to the totals.
+template <int ND, class Fin>
+__global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, int level, Fin fin) {
+  if (!fin.active()) return;
+  const DD *src[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) src[d] = level == 1 ? R->p1[d] : R->p2[d];
+  finish_in_block<ND>(src, count, fin);
+}
+
 // Blocks of the first finishing level (0 when one kernel finishes).
 inline int finish_grid(int G) { return G <= kFinishOne ? 0 : (G + kGroup - 1) / kGroup; }
+
+// ------------------------------------------------------- grid barrier
+// For the persistent solver kernels: every block of a cooperative launch
+// (all co-resident) arrives at a barrier and waits for the others, with no
+// kernel boundary in between.
+//
+// On gfx950 each XCD has its own L2, and the L2s are not kept coherent with
+// each other: a block's stores reach the other XCDs only after its L2 is
+// written back (an agent-scope release fence), and a block sees them only
+// after invalidating its own stale lines (an agent-scope acquire fence).  A
+// write-back walks the whole L2, so the barrier does one per XCD rather than
+// one per block: the blocks of an XCD count themselves in a per-XCD counter
+// (each first waits for its own stores to reach the L2); the last of them
+// (the XCD's leader) releases the L2 and adds 1 to the global counter; when
+// the global count shows every XCD, the leader acquires and publishes the
+// barrier's epoch to its XCD, and every other block of the XCD acquires once
+// it sees that epoch.  The XCD of a block is read from the hardware
+// (XCC_ID); grid_init counts the blocks of each XCD once per launch.
+//
+// Between arrive and wait a block may do work that no other block reads
+// before the next barrier (split phase); it is covered by the next barrier.
+// Waits are bounded: a wait that has polled spin_limit times, or that finds
+// the give-up word set, sets the word and returns false, and the kernel then
+// leaves; every other block's wait then ends too, so the grid drains and the
+// host reports the failure.  `extra` adds arrivals no launch can supply (a
+// barrier that cannot complete, to force that path from the host).
+//
+// The sync block (unsigned long long words, zeroed before the launch; the
+// counters sit on separate 64-byte lines):
+//   [0] arrivals of XCD leaders   [8 + 8x] arrivals on XCD x   [136 + 8x]
+//   released epoch of XCD x       [264 + x] blocks on XCD x    [280]
+//   give-up word
+constexpr int kMaxXcc = 16;
+constexpr int kSyncWords = 288;
+
+struct GridSync {
+  unsigned long long *w;
+  uint32_t extra;
+  int64_t spin_limit;
+};
+
+struct SyncState {  // per block (thread 0's registers)
+  uint64_t passed = 0;    // barriers completed
+  uint32_t xcc = 0;       // this block's XCD
+  uint64_t nx = 0;        // blocks on this XCD
+  uint64_t nxcd = 0;      // XCDs holding blocks
+  bool leader = false;    // last arrival of its XCD at the current barrier
+};
+
+__device__ __forceinline__ unsigned long long sync_load(unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls *p until it reaches t; false if the wait gave up.
+__device__ __forceinline__ bool sync_spin(const GridSync &g, unsigned long long *p, unsigned long long t) {
+  for (int64_t spins = 0;; ++spins) {
+    if (sync_load(p) >= t) return true;
+    if (spins >= g.spin_limit || sync_load(g.w + 280) != 0ull) {
+      __hip_atomic_store(g.w + 280, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Counts the blocks of each XCD; called once by every block at kernel start.
+// Done when the per-XCD counts add up to the grid.
+__device__ __forceinline__ bool grid_init(const GridSync &g, SyncState &ss) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    // HW_REG_XCC_ID (hardware register 20), bits [3:0]
+    ss.xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & uint32_t(kMaxXcc - 1);
+    atomicAdd(g.w + 264 + ss.xcc, 1ull);
+    int good = 1;
+    for (int64_t spins = 0;; ++spins) {
+      unsigned long long total = 0, xcds = 0;
+      for (int x = 0; x < kMaxXcc; ++x) {
+        const unsigned long long c = sync_load(g.w + 264 + x);
+        total += c;
+        xcds += c != 0ull;
+      }
+      if (total == gridDim.x) {
+        ss.nx = sync_load(g.w + 264 + ss.xcc);
+        ss.nxcd = xcds;
+        break;
+      }
+      if (spins >= g.spin_limit || sync_load(g.w + 280) != 0ull) {
+        __hip_atomic_store(g.w + 280, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__device__ __forceinline__ void grid_arrive(const GridSync &g, SyncState &ss) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long e = ss.passed + 1;
+    const unsigned long long mine = atomicAdd(g.w + 8 + 8 * ss.xcc, 1ull) + 1;
+    ss.leader = mine == e * ss.nx;
+    if (ss.leader) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write the XCD's L2 back
+      atomicAdd(g.w, 1ull);
+    }
+  }
+}
+
+__device__ __forceinline__ bool grid_wait(const GridSync &g, SyncState &ss) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    const unsigned long long e = ss.passed + 1;
+    bool good;
+    if (ss.leader) {
+      good = sync_spin(g, g.w, e * ss.nxcd + g.extra);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(g.w + 136 + 8 * ss.xcc, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      good = sync_spin(g, g.w + 136 + 8 * ss.xcc, e);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    ok = good ? 1 : 0;
+  }
+  __syncthreads();
+  ++ss.passed;
+  return ok != 0;
+}
+
+// A block's partial of a persistent kernel's reduction: slot blockIdx.x of
+// half `buf` (0 or 1) of the first-level partials.  Consecutive reductions
+// alternate halves, so a block still reading one reduction's partials never
+// sees them overwritten by a faster block's next reduction (that block must
+// first pass a barrier this block has not reached).
+template <int ND>
+__device__ __forceinline__ void block_partial_half(DD (&v)[ND], Reduce *R, int buf) {
+  block_reduce<ND>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) R->p1[d][buf * int(gridDim.x) + int(blockIdx.x)] = v[d];
+  }
+}
+
+// Every block reduces all blocks' partials of half `buf` in the same fixed
+// order, so every block computes the same totals and scalars.
+template <int ND, class Fin>
+__device__ __forceinline__ void finish_half(Reduce *R, int buf, Fin fin) {
+  const DD *src[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) src[d] = R->p1[d] + buf * int(gridDim.x);
+  finish_in_block<ND>(src, int(gridDim.x), fin);
+  __syncthreads();
+}
 
 // ---------------------------------------------------------------- launch size
 

@@ -68,6 +68,10 @@ struct CsrOp {
   __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
     tiled_rows(*this, sm, load, value, body);
   }
+  template <class Body>
+  __device__ __forceinline__ void own_rows(Body &&body) const {
+    tiled_own_rows(*this, body);
+  }
 
   template <class Fetch, class Consume>
   __device__ __forceinline__ void tile_entries(int32_t r0, int32_t r1, Smem &sm, Fetch &&fetch,

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -38,7 +39,9 @@ struct its_matrix {
   int32_t *color_rows = nullptr;
   std::vector<int32_t> color_off;
   int diag_state = 0;  // CSR: 0 unchecked, 1 every row has a nonzero diagonal, -1 not
-  State *host_state = nullptr;  // pinned snapshot buffer for polling
+  State *host_state = nullptr;  // pinned snapshot buffer for polling (two States and
+                                // one more block for words read back after a
+                                // persistent kernel)
   // Packed copy (its_csr_pack), owned: sliced ELLPACK of col/val and of the
   // low-precision values that were set when it was packed.
   int64_t *sp = nullptr;
@@ -220,13 +223,13 @@ struct Run {
   } while (0)
 
 // ------------------------------------------------------------ workspace
-// [State main][State inner][Reduce scratch][vectors...], every section
-// 256-byte aligned.
+// [State main][State inner][grid-barrier words][Reduce scratch][vectors...],
+// every section 256-byte aligned.
 constexpr size_t kAlign = 256;
 inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t state = 0, state2 = 0, reduce = 0, total = 0;
+  size_t state = 0, state2 = 0, sync = 0, reduce = 0, total = 0;
   size_t off[8] = {};  // offsets of the method's vector regions
   int nreg = 0;
 };
@@ -237,12 +240,14 @@ struct Layout {
 //   CG       : {r, p} interleaved pairs (16), q (8)
 //   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
 //   BiCGStab : {r, u} pairs (16), r' (8), p (8), {r, v} pairs (16), t (8)
-//   CG-NB    : {r, Ap} interleaved pairs (16), p (8), w = A r (8)
-Layout layout_for(int64_t n, int method, int inner_dtype) {
+//   CG-NB    : {r, Ap} interleaved pairs (16), p (8), w = A r (8); persistent:
+//              a second pair buffer (16)
+Layout layout_for(int64_t n, int method, int inner_dtype, int persistent = 0) {
   Layout L;
   L.state = 0;
   L.state2 = up(sizeof(State));
-  L.reduce = L.state2 + up(sizeof(State));
+  L.sync = L.state2 + up(sizeof(State));
+  L.reduce = L.sync + up(sizeof(unsigned long long) * kSyncWords);
   size_t at = L.reduce + up(sizeof(Reduce));
   int per[8] = {};
   switch (method) {
@@ -258,7 +263,10 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
     case ITS_BICGSTAB:
       L.nreg = 5; per[0] = 16; per[1] = 8; per[2] = 8; per[3] = 16; per[4] = 8;
       break;
-    case ITS_CG_NB: L.nreg = 3; per[0] = 16; per[1] = 8; per[2] = 8; break;
+    case ITS_CG_NB:
+      // persistent: a second {r, Ap} pair buffer (iterations alternate)
+      L.nreg = persistent ? 4 : 3; per[0] = 16; per[1] = 8; per[2] = 8; per[3] = 16;
+      break;
     default: break;
   }
   for (int i = 0; i < L.nreg; ++i) {
@@ -272,6 +280,7 @@ Layout layout_for(int64_t n, int method, int inner_dtype) {
 struct WS {
   State *st, *st2;
   Reduce *R;
+  unsigned long long *sync;
   char *base;
   Layout L;
   template <class T>
@@ -281,8 +290,14 @@ struct WS {
 
 WS carve(void *ws, const Layout &L, int64_t) {
   char *b = static_cast<char *>(ws);
-  return {reinterpret_cast<State *>(b + L.state), reinterpret_cast<State *>(b + L.state2),
-          reinterpret_cast<Reduce *>(b + L.reduce), b, L};
+  WS w;
+  w.st = reinterpret_cast<State *>(b + L.state);
+  w.st2 = reinterpret_cast<State *>(b + L.state2);
+  w.R = reinterpret_cast<Reduce *>(b + L.reduce);
+  w.sync = reinterpret_cast<unsigned long long *>(b + L.sync);
+  w.base = b;
+  w.L = L;
+  return w;
 }
 
 // ------------------------------------------------------------ operators
@@ -499,6 +514,56 @@ its_status true_residual(Run &run, const its_matrix *A, const WS &w, const doubl
   return ITS_OK;
 }
 
+// ------------------------------------------------------ persistent loops
+// One cooperative launch of a persistent solver kernel (kernels_persist.hpp)
+// with as many blocks as are co-resident, capped by the work units of the
+// operator (tiles or bricks) and by kPersistBlocks (fewer participants make
+// a cheaper barrier; the environment variable ITS_PERSISTENT_BLOCKS
+// overrides the cap).  The barrier words live in the workspace and are
+// zeroed before the launch.
+
+constexpr int kPersistBlocks = 256;
+
+int64_t env_int(const char *name, int64_t dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char *end = nullptr;
+  const long long r = std::strtoll(v, &end, 10);
+  return (end && *end == '\0') ? int64_t(r) : dflt;
+}
+
+template <class K, class... Args>
+its_status persist_launch(Run &run, State *h, K kernel, int units, const WS &w, Args... args) {
+  int dev = 0, cus = 0, per = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0));
+  int64_t G = std::min<int64_t>(int64_t(per) * cus, env_int("ITS_PERSISTENT_BLOCKS", kPersistBlocks));
+  G = std::min<int64_t>(G, std::max(units, 1));
+  if (G >= 64) G -= G % kXcds;
+  if (G < 1) return fail(ITS_E_UNSUPPORTED, "the persistent kernel does not fit on this device");
+  GridSync gs;
+  gs.w = w.sync;
+  gs.extra = uint32_t(std::max<int64_t>(0, env_int("ITS_BARRIER_TEST_EXTRA", 0)));
+  gs.spin_limit = std::max<int64_t>(0, env_int("ITS_BARRIER_SPIN_LIMIT", int64_t(1) << 24));
+  LAUNCH(run, kClassOther, k_zero_words, 1, w.sync, kSyncWords);
+  void *argv[] = {static_cast<void *>(&args)..., static_cast<void *>(&gs)};
+  run.prof.begin(0, run.s);
+  HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kernel), dim3(unsigned(G)),
+                                     dim3(kBlock), argv, 0, run.s));
+  run.prof.end(run.s);
+  // the solver's State and the give-up word
+  unsigned long long *gave_up = reinterpret_cast<unsigned long long *>(h + 2);
+  HIP_TRY(hipMemcpyAsync(h, w.st, sizeof(State), hipMemcpyDeviceToHost, run.s));
+  HIP_TRY(hipMemcpyAsync(gave_up, w.sync + 280, sizeof(unsigned long long), hipMemcpyDeviceToHost, run.s));
+  HIP_TRY(hipStreamSynchronize(run.s));
+  run.prof.flush();
+  if (*gave_up != 0)
+    return fail(ITS_E_HIP, "persistent kernel: a grid barrier wait gave up after " +
+                               std::to_string(gs.spin_limit) + " polls; x is undefined");
+  return ITS_OK;
+}
+
 // ------------------------------------------------------------------- CG
 
 its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const double *b, double *x,
@@ -525,6 +590,17 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
   else if (!std::isfinite(rr)) flag = kBreakdown;
   else if (o->max_iter <= 0) flag = kMaxIter;
   LAUNCH(run, kClassOther, k_begin, 1, w.st, flag, rr, thr2, (int64_t)o->max_iter);
+  if (flag == kRunning && o->persistent) {
+    s = with_op64(A, [&](auto op) -> its_status {
+      return persist_launch(run, h, k_cg_persist<decltype(op)>, op.grid(), w, op, x, rp, q, b, w.st, w.R);
+    });
+    if (s != ITS_OK) return s;
+    res->status = flag_to_status(h->flag);
+    res->iters = h->k;
+    res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+    res->true_rel_res = std::sqrt(h->dot[2]) / std::sqrt(bb);
+    return ITS_OK;
+  }
   if (flag == kRunning) {
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
@@ -578,6 +654,9 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
       const int GA = op.grid();
       LAUNCH(run, kClassOther, k_cgnb_init<decltype(op)>, GA, op, ra, p, w.R);
       FINISH(run, 1, w.R, GA, (FinCgnbInit{w.st}));
+      if (o->persistent)
+        return persist_launch(run, h, k_cgnb_persist<decltype(op)>, GA, w, op, x, ra, w.reg<double2_t>(3), p, wv, b,
+                              w.st, w.R);
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, k_cgnb_x<decltype(op)>, GA, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCgnbX{w.st}));
@@ -594,6 +673,10 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
   res->status = flag_to_status(h->flag);
   res->iters = h->k;
   res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  if (flag == kRunning && o->persistent) {  // the kernel formed the true residual
+    res->true_rel_res = std::sqrt(h->dot[2]) / std::sqrt(bb);
+    return ITS_OK;
+  }
   return true_residual(run, A, w, b, x, h, bb, res);
 }
 
@@ -708,6 +791,15 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
     const int32_t paper = o->restart_mode == ITS_RESTART_PAPER;
     s = with_op64(A, [&](auto op) -> its_status {
       const int GA = op.grid();
+      if (o->persistent) {
+        // BiCGStab-B1's split-phase schedule (ITS_BICGSTAB_SPLIT=0: the same
+        // updates after the waits, classical BiCGStab's blocking points)
+        if (env_int("ITS_BICGSTAB_SPLIT", 1) != 0)
+          return persist_launch(run, h, k_bicg_persist<decltype(op), true>, GA, w, op, x, ru, rs, p, rv, t, b,
+                                w.st, w.R, rt2, paper);
+        return persist_launch(run, h, k_bicg_persist<decltype(op), false>, GA, w, op, x, ru, rs, p, rv, t, b,
+                              w.st, w.R, rt2, paper);
+      }
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double2_t *)ru, rs, p, rv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
@@ -727,6 +819,10 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
   res->iters = h->k;
   res->restarts = h->restarts;
   res->rel_res = std::sqrt(h->rho) / std::sqrt(bb);
+  if (flag == kRunning && o->persistent) {  // the kernel formed the true residual
+    res->true_rel_res = std::sqrt(h->dot[2]) / std::sqrt(bb);
+    return ITS_OK;
+  }
   return true_residual(run, A, w, b, x, h, bb, res);
 }
 
@@ -922,6 +1018,7 @@ bool options_ok(const its_options *o, std::string &why) {
   if (o->profile < 0) { why = "profile must be >= 0"; return false; }
   if (o->transpose != 0 && o->transpose != 1) { why = "transpose must be 0 or 1"; return false; }
   if (o->graph != 0 && o->graph != 1) { why = "graph must be 0 or 1"; return false; }
+  if (o->persistent != 0 && o->persistent != 1) { why = "persistent must be 0 or 1"; return false; }
   return true;
 }
 
@@ -967,12 +1064,12 @@ static its_status new_matrix(its_matrix **out) {
   its_matrix *A = new (std::nothrow) its_matrix();
   if (!A) return fail(ITS_E_INVALID, "out of host memory");
   void *p = nullptr;
-  if (hipHostMalloc(&p, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&p, 3 * sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete A;
     return fail(ITS_E_HIP, "hipHostMalloc of the state snapshot failed");
   }
   A->host_state = static_cast<State *>(p);
-  std::memset(A->host_state, 0, sizeof(State));
+  std::memset(A->host_state, 0, 3 * sizeof(State));
   *out = A;
   return ITS_OK;
 }
@@ -1550,7 +1647,7 @@ its_status its_workspace_size(const its_matrix *A, const its_options *o, size_t 
   if (!A || !o || !bytes) return fail(ITS_E_INVALID, "null argument");
   std::string why;
   if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
-  *bytes = layout_for(A->n, o->method, o->inner_dtype).total;
+  *bytes = layout_for(A->n, o->method, o->inner_dtype, o->persistent).total;
   return ITS_OK;
 }
 
@@ -1605,7 +1702,7 @@ its_status its_solve_noalloc(const its_matrix *A, const its_options *o, const do
   if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
   if (o->graph != 0) return fail(ITS_E_UNSUPPORTED, "its_solve_noalloc does not capture graphs (graph must be 0)");
   if (o->profile != 0) return fail(ITS_E_UNSUPPORTED, "its_solve_noalloc does not profile (profile must be 0)");
-  const size_t need = layout_for(A->n, o->method, o->inner_dtype).total;
+  const size_t need = layout_for(A->n, o->method, o->inner_dtype, o->persistent).total;
   if (need > kScratchBytes)
     return fail(ITS_E_WORKSPACE, "its_solve_noalloc: this solve needs " + std::to_string(need) +
                                      " bytes of scratch; the static buffer holds " +
@@ -1651,10 +1748,13 @@ static its_status solve_impl(const its_matrix *Ac, const its_options *o, const d
   if (!options_ok(o, why)) return fail(ITS_E_INVALID, why);
   if (A->n > 0 && (!b || !x)) return fail(ITS_E_INVALID, "null vector");
   if (A->n > 0 && b == x) return fail(ITS_E_INVALID, "b and x alias");
-  const Layout L = layout_for(A->n, o->method, o->inner_dtype);
+  const Layout L = layout_for(A->n, o->method, o->inner_dtype, o->persistent);
   if (!workspace || ws_bytes < L.total) return fail(ITS_E_WORKSPACE, "workspace missing or too small");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(ITS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (o->persistent && !((o->method == ITS_CG && o->inner_dtype == ITS_F64) || o->method == ITS_CG_NB ||
+                         o->method == ITS_BICGSTAB))
+    return fail(ITS_E_UNSUPPORTED, "persistent is for FP64 CG, CG-NB and BiCGStab");
   if ((o->method == ITS_SGS) && A->kind == kCsr && A->ncolors == 0)
     return fail(ITS_E_INVALID, "Gauss-Seidel on CSR needs its_csr_set_colors");
   std::memset(res, 0, sizeof(*res));

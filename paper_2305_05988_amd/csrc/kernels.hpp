@@ -10,6 +10,7 @@
 #include "kernels_cg.hpp"
 #include "kernels_cgnb.hpp"
 #include "kernels_ir.hpp"
+#include "kernels_persist.hpp"
 #include "kernels_relax.hpp"
 #include "kernels_util.hpp"
 #include "sell.hpp"

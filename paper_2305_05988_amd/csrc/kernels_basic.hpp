@@ -15,6 +15,11 @@ __global__ void k_reset(State *st, int nstates, Reduce *R) {
   for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0u;
 }
 
+// Zero `count` 64-bit words (one block).
+__global__ void k_zero_words(unsigned long long *w, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) w[i] = 0ull;
+}
+
 // ------------------------------------------------------ scalar updates
 // Each reducing pass stores per-block partials; the finishing kernel that
 // follows it on the stream reduces them and applies one of these.

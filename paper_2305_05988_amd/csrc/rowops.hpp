@@ -50,6 +50,14 @@ __device__ __forceinline__ void tiled_rows(const Op &A, typename Op::Smem &sm, L
   });
 }
 
+// The rows a thread owns in tiled_rows(), in the same order: body(i).  A
+// pass that walks own_rows() after a rows() pass touches exactly the rows
+// this thread handled there.
+template <class Op, class Body>
+__device__ __forceinline__ void tiled_own_rows(const Op &A, Body &&body) {
+  for_rows(A.n, body);
+}
+
 __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ float widen(__half v) { return __half2float(v); }

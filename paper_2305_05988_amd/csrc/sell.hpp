@@ -125,6 +125,10 @@ struct SellOp {
   __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
     tiled_rows(*this, sm, load, value, body);
   }
+  template <class Body>
+  __device__ __forceinline__ void own_rows(Body &&body) const {
+    tiled_own_rows(*this, body);
+  }
 
   // Entries g .. g + W - 1 of the lane's row in a slice of width w (g even):
   // all column and value loads, then all gathers, then the chain.  W is a

@@ -53,6 +53,23 @@ struct VarCoefOp {
     return (2.0 * a * b) / (a + b);
   }
 
+  // The rows a thread owns in rows(), in the same order: body(i).
+  template <class Body>
+  __device__ __forceinline__ void own_rows(Body &&body) const {
+    const int64_t nbricks = int64_t(nbx) * nby * nbz;
+    const Sched sc = my_tiles(nbricks);
+    const int t = threadIdx.x, lane = t & 63, wy = t >> 6;
+    const int32_t nxy = nx * ny;
+    for (int64_t bi = sc.begin; bi < sc.end; bi += sc.stride) {
+      const int32_t bx = int32_t(bi % nbx), by = int32_t((bi / nbx) % nby);
+      const int32_t bz = int32_t(bi / (int64_t(nbx) * nby));
+      const int32_t gx = bx * kTX + lane, gy = by * kTY + wy;
+      if (gx >= nx || gy >= ny) continue;
+      const int32_t z0 = bz * zb, z1 = min(nz, z0 + zb);
+      for (int32_t z = z0; z < z1; ++z) body(gx + nx * gy + nxy * z);
+    }
+  }
+
   // The 2.5-D sweep of the constant stencil, with the coefficients staged
   // beside the vector values.
   template <class Load, class Value, class Body>
