@@ -161,10 +161,19 @@ struct SellOp {
       if constexpr ((W - F) % 2 == 1) vj[W - 1] = ld_nt(val + sell_slot4(base, w, g + W - 1, lane));
     }
     if (Off) {
+      // the group's descriptors are wave-uniform: all of them are loaded
+      // before any is used, so they arrive together (a load under the
+      // lane's mask test would make each wait for the previous one)
       const int64_t k = (base >> 6) + g;
+      int32_t offs[W];
+      uint64_t msk[W];
 #pragma unroll
-      for (int u = 0; u < W; ++u)
-        cj[u] = (smask[k + u] >> lane) & 1u ? row + soff[k + u] : -1;
+      for (int u = 0; u < W; ++u) {
+        offs[u] = soff[k + u];
+        msk[u] = smask[k + u];
+      }
+#pragma unroll
+      for (int u = 0; u < W; ++u) cj[u] = (msk[u] >> lane) & 1u ? row + offs[u] : -1;
     }
     // padding slots fetch a stand-in row (not consumed)
     decltype(fetch(0)) xj[W];
