@@ -352,7 +352,7 @@ const char *its_last_error(void); /* message of this thread's last error */
    z planes one brick of the SpMV pass covers, by timing that pass on the
    first solve.  Each (system, rhs) follows exactly the arithmetic of the
    single-system CG (the same iterates, bit for bit) and stops on its own
-   test; m = check_every iterations (default 16) are captured in one HIP
+   test; m = check_every iterations (default 64) are captured in one HIP
    graph that is replayed until every (system, rhs) has stopped.
 
    Layout: the systems' cells are concatenated in system order; vectors

@@ -434,7 +434,9 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
   BHIP(hipGetLastError());
   BHIP(hipMemcpyAsync(B->h_count, V.nact, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
-  const int m = o->check_every > 0 ? o->check_every : 16;
+  // m = 64 iterations per replay: about ten host polls per solve (the
+  // replays cost the same with 16)
+  const int m = o->check_every > 0 ? o->check_every : 64;
   int64_t replays = 0;
   if (*B->h_count > 0) {
     // one graph: m iterations (the four CG kernels, then the gathering of

@@ -3,6 +3,7 @@
 // those coefficients (see rowops.hpp for the row-sweep contract).
 #pragma once
 
+#include "brick.hpp"
 #include "rowops.hpp"
 
 namespace its {
@@ -22,32 +23,22 @@ struct VarCoefOp {
   const double *__restrict__ k;
   int32_t nbx = 0, nby = 0, nbz = 0, zb = 1;
 
-  static constexpr int kTX = 64, kTY = kBlock / 64;
-  static constexpr int kCols = kTX + 2, kTileRows = kTY + 2, kPlane = kCols * kTileRows;
-  static constexpr int kSlots = 4;
+  // the brick sweep of brick.hpp, with the coefficients staged beside the
+  // vector values
   struct Smem {
-    double v[kSlots][kPlane];
-    double kc[kSlots][kPlane];
+    double v[kBrickSlots][kBrickPlane];
+    double kc[kBrickSlots][kBrickPlane];
   };
 
   void plan() {
-    nbx = (nx + kTX - 1) / kTX;
-    nby = (ny + kTY - 1) / kTY;
-    const int64_t nxy = int64_t(nbx) * nby;
-    int64_t chunks = nxy > 0 ? (2048 + nxy - 1) / nxy : 1;
-    if (chunks > nz) chunks = nz;
-    if (chunks < 1) chunks = 1;
-    zb = int32_t((nz + chunks - 1) / chunks);
-    if (zb < 1) zb = 1;
-    nbz = (nz + zb - 1) / zb;
+    const BrickGeom g = brick_plan(nx, ny, nz);
+    nbx = g.nbx;
+    nby = g.nby;
+    nbz = g.nbz;
+    zb = g.zb;
   }
-  int grid() const {
-    int64_t b = int64_t(nbx) * nby * nbz;
-    if (b < 1) b = 1;
-    int g = int(b < kMaxGrid ? b : kMaxGrid);
-    if (g >= 64) g -= g % kXcds;
-    return g;
-  }
+  __host__ __device__ BrickGeom geom() const { return {nx, ny, nz, nbx, nby, nbz, zb}; }
+  int grid() const { return brick_grid(geom()); }
 
   __device__ static __forceinline__ double face(double a, double b) {
     return (2.0 * a * b) / (a + b);
@@ -56,103 +47,51 @@ struct VarCoefOp {
   // The rows a thread owns in rows(), in the same order: body(i).
   template <class Body>
   __device__ __forceinline__ void own_rows(Body &&body) const {
-    const int64_t nbricks = int64_t(nbx) * nby * nbz;
-    const Sched sc = my_tiles(nbricks);
-    const int t = threadIdx.x, lane = t & 63, wy = t >> 6;
-    const int32_t nxy = nx * ny;
-    for (int64_t bi = sc.begin; bi < sc.end; bi += sc.stride) {
-      const int32_t bx = int32_t(bi % nbx), by = int32_t((bi / nbx) % nby);
-      const int32_t bz = int32_t(bi / (int64_t(nbx) * nby));
-      const int32_t gx = bx * kTX + lane, gy = by * kTY + wy;
-      if (gx >= nx || gy >= ny) continue;
-      const int32_t z0 = bz * zb, z1 = min(nz, z0 + zb);
-      for (int32_t z = z0; z < z1; ++z) body(gx + nx * gy + nxy * z);
-    }
+    brick_own_rows(geom(), body);
   }
 
-  // The 2.5-D sweep of the constant stencil, with the coefficients staged
-  // beside the vector values.
   template <class Load, class Value, class Body>
   __device__ __forceinline__ void rows(Smem &sm, Load &&load, Value &&value, Body &&body) const {
     using Raw = decltype(load(0));
-    constexpr int kPer = (kPlane + kBlock - 1) / kBlock;
-    const int64_t nbricks = int64_t(nbx) * nby * nbz;
-    const Sched sc = my_tiles(nbricks);
-    const int t = threadIdx.x, lane = t & 63, wy = t >> 6;
+    struct Point {
+      Raw v;
+      double k;
+    };
     const int32_t nxy = nx * ny;
-    for (int64_t bi = sc.begin; bi < sc.end; bi += sc.stride) {
-      const int32_t bx = int32_t(bi % nbx), by = int32_t((bi / nbx) % nby);
-      const int32_t bz = int32_t(bi / (int64_t(nbx) * nby));
-      const int32_t x0 = bx * kTX, y0 = by * kTY, z0 = bz * zb, z1 = min(nz, z0 + zb);
-      auto tile_row = [&](int q, int32_t z) -> int32_t {
-        const int32_t gy = y0 - 1 + q / kCols, gx = x0 - 1 + q % kCols;
-        if (q >= kPlane || z < 0 || z >= nz || gx < 0 || gx >= nx || gy < 0 || gy >= ny) return -1;
-        return gx + nx * gy + nxy * z;
-      };
-      Raw rv[kPer];
-      double rk[kPer];
-      auto issue = [&](int32_t z) {
+    brick_march(
+        geom(), [&](int32_t r) { return Point{load(r), k[r]}; },
+        [&](int slot, int q, const Point &p) {
+          sm.v[slot][q] = value(p.v);
+          sm.kc[slot][q] = p.k;
+        },
+        [&](int32_t i, bool valid, int32_t gx, int32_t gy, int32_t z, int sm1, int s0, int sp1, int c0) {
+          auto entries = [&](auto &&consume) {
+            if (!valid) return;
+            const double kc = sm.kc[s0][c0];
+            const bool in[6] = {z > 0, gy > 0, gx > 0, gx < nx - 1, gy < ny - 1, z < nz - 1};
+            const double kn[6] = {sm.kc[sm1][c0],     sm.kc[s0][c0 - kBrickCols], sm.kc[s0][c0 - 1],
+                                  sm.kc[s0][c0 + 1], sm.kc[s0][c0 + kBrickCols], sm.kc[sp1][c0]};
+            const double xv[7] = {sm.v[sm1][c0],     sm.v[s0][c0 - kBrickCols], sm.v[s0][c0 - 1],
+                                  sm.v[s0][c0],      sm.v[s0][c0 + 1],          sm.v[s0][c0 + kBrickCols],
+                                  sm.v[sp1][c0]};
+            double f[6];
+            double diag = 0.0;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-          const int32_t r = tile_row(t + u * kBlock, z);
-          const int32_t rr = r >= 0 ? r : 0;
-          rv[u] = load(rr);
-          rk[u] = k[rr];
-        }
-      };
-      auto put = [&](int32_t z) {
-        double *dv = sm.v[z & (kSlots - 1)];
-        double *dk = sm.kc[z & (kSlots - 1)];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u)
-          if (t + u * kBlock < kPlane) {
-            dv[t + u * kBlock] = value(rv[u]);
-            dk[t + u * kBlock] = rk[u];
-          }
-      };
-      for (int32_t z = max(z0 - 1, 0); z <= min(z0 + 1, nz - 1); ++z) {
-        issue(z);
-        put(z);
-      }
-      __syncthreads();
-      const int32_t gx = x0 + lane, gy = y0 + wy;
-      const bool valid = gx < nx && gy < ny;
-      const int c0 = (wy + 1) * kCols + lane + 1;
-      for (int32_t z = z0; z < z1; ++z) {
-        const int32_t zn = z + 2;
-        const bool pf = zn <= z1 && zn < nz;
-        if (pf) issue(zn);
-        const int sm1 = (z - 1) & (kSlots - 1), s0 = z & (kSlots - 1), sp1 = (z + 1) & (kSlots - 1);
-        const int32_t i = gx + nx * gy + nxy * z;
-        auto entries = [&](auto &&consume) {
-          if (!valid) return;
-          const double kc = sm.kc[s0][c0];
-          const bool in[6] = {z > 0, gy > 0, gx > 0, gx < nx - 1, gy < ny - 1, z < nz - 1};
-          const double kn[6] = {sm.kc[sm1][c0], sm.kc[s0][c0 - kCols], sm.kc[s0][c0 - 1],
-                                sm.kc[s0][c0 + 1], sm.kc[s0][c0 + kCols], sm.kc[sp1][c0]};
-          const double xv[7] = {sm.v[sm1][c0], sm.v[s0][c0 - kCols], sm.v[s0][c0 - 1], sm.v[s0][c0],
-                                sm.v[s0][c0 + 1], sm.v[s0][c0 + kCols], sm.v[sp1][c0]};
-          double f[6];
-          double diag = 0.0;
-#pragma unroll
-          for (int o = 0; o < 6; ++o) {
-            f[o] = !in[o] ? kc : (o < 3 ? face(kn[o], kc) : face(kc, kn[o]));
-            diag = diag + f[o];
-          }
-          if (in[0]) consume(i - nxy, -f[0], xv[0]);
-          if (in[1]) consume(i - nx, -f[1], xv[1]);
-          if (in[2]) consume(i - 1, -f[2], xv[2]);
-          consume(i, diag, xv[3]);
-          if (in[3]) consume(i + 1, -f[3], xv[4]);
-          if (in[4]) consume(i + nx, -f[4], xv[5]);
-          if (in[5]) consume(i + nxy, -f[5], xv[6]);
-        };
-        auto own = [&]() -> double { return sm.v[s0][c0]; };
-        body(i, valid, entries, own);
-        if (pf) put(zn);
-        __syncthreads();
-      }
-    }
+            for (int o = 0; o < 6; ++o) {
+              f[o] = !in[o] ? kc : (o < 3 ? face(kn[o], kc) : face(kc, kn[o]));
+              diag = diag + f[o];
+            }
+            if (in[0]) consume(i - nxy, -f[0], xv[0]);
+            if (in[1]) consume(i - nx, -f[1], xv[1]);
+            if (in[2]) consume(i - 1, -f[2], xv[2]);
+            consume(i, diag, xv[3]);
+            if (in[3]) consume(i + 1, -f[3], xv[4]);
+            if (in[4]) consume(i + nx, -f[4], xv[5]);
+            if (in[5]) consume(i + nxy, -f[5], xv[6]);
+          };
+          auto own = [&]() -> double { return sm.v[s0][c0]; };
+          body(i, valid, entries, own);
+        });
   }
 };
 

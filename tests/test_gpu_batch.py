@@ -117,7 +117,7 @@ def test_batch_autotuner_reports_its_choice():
     dims, kc, b, B = _batch(4, 8, lo=8, hi=16, seed=18)
     x, info = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
     assert info.planes_per_brick in (4, 8, 16, 32, 64) and info.tune_ms > 0
-    assert info.tiles_per_item == 16
+    assert info.tiles_per_item == 16 and info.graph_iters == 64
     x, info2 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
     assert info2.planes_per_brick == info.planes_per_brick and info2.tune_ms == info.tune_ms
 
