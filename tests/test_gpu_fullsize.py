@@ -89,6 +89,27 @@ def test_full_size_ir_27pt_192(lowp):
     assert np.array_equal(host(x), ref)
 
 
+@pytest.mark.parametrize("lowp", ["f32", "f16"])
+def test_ir_7pt_blocks_walk_several_tiles(lowp):
+    # 128 x 151 x 211 rows: x-lines of two whole slices, so every slice is an
+    # offset slice; 15931 tiles over 4096 blocks, so blocks walk three or
+    # four tiles (both ends of the two-tile loop), and the last tile holds
+    # two slices (the other two lie past the last row)
+    g = (128, 151, 211)
+    say(f"mixed-precision refinement ({lowp} values), 3 inner iterations, 7-point {g}")
+    Acsr = inputs.poisson7_csr(*g)
+    A = its().CSRMatrix.from_numpy(*Acsr, validate=False, lowp=(lowp,), pack=True)
+    assert A.packed_column_slots == 0  # every slice an offset slice
+    b = oracle.spmv(Acsr, inputs.uniform_vector(Acsr[0].size - 1, 4))
+    lo = Acsr[2].astype(np.float32 if lowp == "f32" else np.float16)
+    for k in (1, 3):
+        ref, rr = oracle.ir_cg(Acsr, lo, b, rtol=1e-10, max_iter=k, inner_rtol=1e-4)
+        x, info = its().solve(A, dev(b), method="cg", rtol=1e-10, max_iter=k, inner_dtype=lowp,
+                              inner_rtol=1e-4)
+        assert info.inner_iters == rr.inner_iters == k
+        assert np.array_equal(host(x), ref)
+
+
 def test_full_size_varcoef_128():
     say("variable-coefficient CG, 2 iterations, and the gradient kernel, 128^3")
     g = (128, 128, 128)
