@@ -221,9 +221,11 @@ int64_t its_csr_packed_column_slots(const its_matrix *A);
    in its_matrix_destroy. */
 its_status its_csr_set_colors(its_matrix *A, const uint8_t *color, int32_t ncolors, void *stream);
 
-/* Matrix-free constant-coefficient stencil on an nx*ny*nz grid, rows
-   numbered i + nx*(j + ny*k), neighbours outside the grid omitted
-   (Dirichlet).  npts = 7 or 27.  coef (host, copied): one value per offset
+/* Matrix-free constant-coefficient stencil on an nx*ny*nz grid: the 7- and
+   27-point centred stencils on a structured hexahedral mesh that give the
+   paper's two sparsity levels (Section 3.1, with the element counts per row
+   of its touched-elements estimate).  Rows numbered i + nx*(j + ny*k),
+   neighbours outside the grid omitted (Dirichlet).  npts = 7 or 27.  coef (host, copied): one value per offset
    in ascending column order -- 7-point: (k-1, j-1, i-1, centre, i+1, j+1,
    k+1); 27-point: dk outer, dj, di inner, each -1..1.  Gauss-Seidel uses the
    red-black colouring (i+j+k) mod 2 for 7 points and the 8 colours
@@ -270,9 +272,11 @@ its_status its_stencil_plan(const its_matrix *A, int32_t *plan);
 
 /* ----------------------------------------------------------------- kernels */
 
-/* y = A x, each row a fused multiply-add chain over its entries in stored
+/* y = A x: the sparse matrix-vector product that each method of Section 3.1
+   applies once (CG, Jacobi) or twice (BiCGStab, Algorithm 2) per iteration.
+   Each row is a fused multiply-add chain over its entries in stored
    (ascending column) order starting from +0.  x, y: device, length n, not
-   aliased. */
+   aliased.  Errors: ITS_E_INVALID for a null handle or vector, or x == y. */
 its_status its_spmv(const its_matrix *A, const double *x, double *y, void *stream);
 
 /* Dot product (the paper's scalar products): the sum of x_i*y_i computed
@@ -287,7 +291,10 @@ its_status its_dot(int64_t n, const double *x, const double *y, double *result, 
 
 /* ------------------------------------------------------------------- solve */
 
-/* Device workspace in bytes needed by its_solve for this matrix/options. */
+/* Device workspace in bytes needed by its_solve for this matrix/options:
+   the vectors the chosen method keeps besides x and b (the r, p, q, ... of
+   Algorithms 1-2 and their classical counterparts, Section 3.1), the device
+   State blocks and the reduction partials of its dot products. */
 its_status its_workspace_size(const its_matrix *A, const its_options *opts, size_t *bytes);
 
 /* Solves A x = b.  b: device, n.  x: device, n, in = x0, out = solution.

@@ -53,6 +53,7 @@ struct its_matrix {
   uint64_t *smask = nullptr;
   int64_t sell_entries = 0;
   int64_t sell_col_slots = 0;  // slots of the slices that store columns
+  int32_t sell_wmax = 0;       // widest slice
   double pack_fill = 0.0;  // max_fill of the last its_csr_pack (0: not packed)
   // Gauss-Seidel: each colour's rows packed the same way, in colour order
   struct ColorPack {
@@ -112,6 +113,7 @@ static void free_packed(its_matrix *A) {
   A->smask = nullptr;
   A->sell_entries = 0;
   A->sell_col_slots = 0;
+  A->sell_wmax = 0;
   A->pack_fill = 0.0;
   free_color_packs(A);
 }
@@ -228,6 +230,8 @@ struct Run {
 constexpr size_t kAlign = 256;
 inline size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int kGuardPairs = 32;  // 256 bytes of FP32 pairs
+
 struct Layout {
   size_t state = 0, state2 = 0, sync = 0, reduce = 0, total = 0;
   size_t off[8] = {};  // offsets of the method's vector regions
@@ -238,7 +242,7 @@ struct Layout {
 //   Jacobi   : x ping-pong buffer (8)
 //   SGS      : the saved black rows of the iterate under test (8; CSR, two colours)
 //   CG       : {r, p} interleaved pairs (16), q (8)
-//   IR-CG    : r (8), {r, p} FP32 pairs (8), q (4), d (4)
+//   IR-CG    : r (8), {r, p} FP32 pairs (8, + 256 bytes of guard pairs at each end), q (4), d (4)
 //   BiCGStab : {r, u} pairs (16), r' (8), p (8), {r, v} pairs (16), t (8)
 //   CG-NB    : {r, Ap} interleaved pairs (16), p (8), w = A r (8); persistent:
 //              a second pair buffer (16)
@@ -269,9 +273,12 @@ Layout layout_for(int64_t n, int method, int inner_dtype, int persistent = 0) {
       break;
     default: break;
   }
+  // the refinement's FP32 pairs carry two guard pairs at each end
+  size_t pad[8] = {};
+  if (method == ITS_CG && inner_dtype != ITS_F64) pad[1] = 2 * kGuardPairs * sizeof(float2_t);
   for (int i = 0; i < L.nreg; ++i) {
     L.off[i] = at;
-    at += up(size_t(n) * size_t(per[i]));
+    at += up(size_t(n) * size_t(per[i]) + pad[i]);
   }
   L.total = at;
   return L;
@@ -691,7 +698,10 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
   if (A->kind == kCsr && ((dt == ITS_F32 && !A->val32) || (dt == ITS_F16 && !A->val16)))
     return fail(ITS_E_INVALID, "mixed precision needs its_csr_set_lowp values of that dtype");
   double *r = w.v64(0);
-  float2_t *rhp = w.reg<float2_t>(1);  // inner {r, p} pairs
+  // inner {r, p} pairs, with guard pairs before index 0 and after index
+  // n - 1 (the two-rows-per-lane pass reads a pair past either end); 256
+  // bytes of them in front keep the pairs' alignment
+  float2_t *rhp = w.reg<float2_t>(1) + kGuardPairs;
   float *q = w.reg<float>(2), *d = w.reg<float>(3);
   double bb, rr;
   its_status s = prologue(run, A, w, b, x, r, 1, h, bb, rr);
@@ -733,8 +743,23 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
     if (!(rho_i <= ithr2)) {
       LAUNCH(run, kClassOther, k_begin, 1, w.st2, (int32_t)kRunning, rho_i, ithr2, budget);
       s = with_op32(A, dt, [&](auto op) -> its_status {
-        const int GA = op.grid();
+        // two rows per lane where it pays (measured): FP16 values, or
+        // slices wider than one group of seven entries
+        bool pairs = false;
+        if constexpr (PairWalk<decltype(op)>::value)
+          pairs = sizeof(typename decltype(op)::value_type) == 2 || A->sell_wmax > 7;
+        int GA = op.grid();
+        if constexpr (PairWalk<decltype(op)>::value)
+          if (pairs) GA = op.grid_pairs(A->sell_wmax > 7);
         return iterate(run, w.st2, h, budget, batch_size(o, n), [&](int64_t) -> its_status {
+          if constexpr (PairWalk<decltype(op)>::value)
+            if (pairs) {
+              LAUNCH(run, 0, (k_cg_pass1_pairs<decltype(op)>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
+              FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
+              LAUNCH(run, 1, k_cg_pass2_f32x2, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
+              FINISH(run, 1, w.R, G2, (FinCg2{w.st2}));
+              return ITS_OK;
+            }
           LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
           LAUNCH(run, 1, k_cg_pass2_f32x2, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
@@ -1375,6 +1400,7 @@ struct PackOut {
   int32_t *soff = nullptr;
   uint64_t *smask = nullptr;
   int64_t slots = 0;
+  int32_t wmax = 0;
   int64_t col_slots = 0;
   void release() {
     if (sp) (void)hipFree(sp);
@@ -1476,6 +1502,7 @@ static its_status pack_rows(const its_matrix *A, const int32_t *rows, int64_t co
     return fail(ITS_E_HIP, std::string("packing: ") + hipGetErrorString(e));
   }
   P.slots = total;
+  for (int32_t w : hw) P.wmax = std::max(P.wmax, w);
   out = P;
   return ITS_OK;
 }
@@ -1536,6 +1563,7 @@ its_status its_csr_pack(its_matrix *A, double max_fill, void *stream) {
   A->smask = P.smask;
   A->sell_entries = P.slots;
   A->sell_col_slots = P.col_slots;
+  A->sell_wmax = P.wmax;
   A->pack_fill = max_fill;
   // A^T alike where its rows fit max_fill (else it stays in CSR form)
   if (A->tr) (void)its_csr_pack(A->tr, max_fill, stream);

@@ -57,6 +57,52 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
   block_partial<1>(v, R);
 }
 
+// Pass 1 of the refinement's FP32 inner CG on an FP32/FP16 offset-slice
+// layout, two rows per lane (SellOp::walk_pairs): for each row the
+// arithmetic of k_cg_pass1.  rp must be readable at indices -1 and n.
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_cg_pass1_pairs(Op A, const float2_t *rp, float *q,
+                                                           const State *st, Reduce *R) {
+  if (st->flag != kRunning) return;
+  const bool first = st->k == 0;
+  const float beta = float(st->beta);
+  auto pv = [&](const float2_t &v) -> float { return first ? v.x : fmaT(beta, v.y, v.x); };
+  Dot2 a;
+  A.walk_pairs(rp, [&](int32_t i0, int32_t i1, bool valid0, bool valid1, auto &&entries) {
+    float acc0 = 0.0f, acc1 = 0.0f, p0 = 0.0f, p1 = 0.0f;
+    bool have0 = false, have1 = false;  // p_i taken from the row's diagonal entry
+    entries(
+        [&](int32_t j, float av, const float2_t &raw) {
+          const float pj = pv(raw);
+          acc0 = fmaT(av, pj, acc0);
+          if (j == i0) {
+            p0 = pj;
+            have0 = true;
+          }
+        },
+        [&](int32_t j, float av, const float2_t &raw) {
+          const float pj = pv(raw);
+          acc1 = fmaT(av, pj, acc1);
+          if (j == i1) {
+            p1 = pj;
+            have1 = true;
+          }
+        });
+    if (valid0) {
+      st_nt(q + i0, acc0);
+      if (!have0) p0 = pv(rp[i0]);
+      a.add(double(p0), double(acc0));
+    }
+    if (valid1) {
+      st_nt(q + i1, acc1);
+      if (!have1) p1 = pv(rp[i1]);
+      a.add(double(p1), double(acc1));
+    }
+  });
+  DD v[1] = {a.get()};
+  block_partial<1>(v, R);
+}
+
 // alpha = rho / (p.q); p.q = 0 or non-finite is a breakdown.
 struct FinCg1 {
   State *st;

@@ -103,10 +103,55 @@ __device__ __forceinline__ void ld_quad(const __half *p, __half *v) {
   v[3] = __builtin_bit_cast(__half, static_cast<unsigned short>(q.y >> 16));
 }
 
+// N consecutive low-precision values (N = 2, 4 or 8) with the widest
+// accesses that cover them (one 4-, 8- or 16-byte load for FP16; one or two
+// 8- or 16-byte loads for FP32).  p must be aligned to the run's size (16
+// bytes at most).
+typedef uint32_t uint4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __half half_bits(uint32_t w, int k) {
+  return __builtin_bit_cast(__half, static_cast<unsigned short>(w >> (16 * k)));
+}
+template <int N>
+__device__ __forceinline__ void ld_run(const __half *p, __half *v) {
+  if constexpr (N == 8) {
+    const uint4_t q = ld_nt(reinterpret_cast<const uint4_t *>(p));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = half_bits(q[k >> 1], k & 1);
+  } else if constexpr (N == 4) {
+    const uint2_t q = ld_nt(reinterpret_cast<const uint2_t *>(p));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = half_bits(q[k >> 1], k & 1);
+  } else {
+    static_assert(N == 2, "runs of 2, 4 or 8");
+    const uint32_t q = ld_nt(reinterpret_cast<const uint32_t *>(p));
+    v[0] = half_bits(q, 0);
+    v[1] = half_bits(q, 1);
+  }
+}
+template <int N>
+__device__ __forceinline__ void ld_run(const float *p, float *v) {
+  if constexpr (N == 2) {
+    const float2_t q = ld_nt(reinterpret_cast<const float2_t *>(p));
+    v[0] = q.x;
+    v[1] = q.y;
+  } else {
+    static_assert(N == 4 || N == 8, "runs of 2, 4 or 8");
+#pragma unroll
+    for (int h = 0; h < N / 4; ++h) {
+      const float4_t q = ld_nt(reinterpret_cast<const float4_t *>(p + 4 * h));
+      v[4 * h] = q.x;
+      v[4 * h + 1] = q.y;
+      v[4 * h + 2] = q.z;
+      v[4 * h + 3] = q.w;
+    }
+  }
+}
+
 // OffOnly: every non-empty slice is an offset slice (the layout stores no
 // columns), so the explicit-column path is not compiled in.
 template <class V, class T, bool OffOnly = false>
 struct SellOp {
+  using value_type = V;
   const int64_t *__restrict__ sp;
   const int32_t *__restrict__ col;
   const V *__restrict__ val;
@@ -128,6 +173,140 @@ struct SellOp {
   template <class Body>
   __device__ __forceinline__ void own_rows(Body &&body) const {
     tiled_own_rows(*this, body);
+  }
+
+  // ------------------------------------------------ two rows per lane
+  // The refinement's FP32/FP16 pass moves few bytes per row, and one row per
+  // lane leaves it bound by memory instructions: each entry costs a wave a
+  // gather of 8-byte {r, p} pairs.  On offset-slice layouts a wave can take
+  // two slices at once, lane l holding rows 2l' and 2l' + 1 (l' = l mod 32)
+  // of slice 2k + l / 32: both rows have the same column offsets, so one
+  // 16-byte gather at row + d brings both rows' pairs for offset d, and the
+  // layout already places the two rows' values side by side (one load for
+  // four entries of both rows).  Tiles are 512 rows (two slices per wave).
+  // When the two slices differ in width (a grid boundary between them, or
+  // the matrix's last slice) the tile takes them one row per lane instead.
+  //
+  // body(i0, i1, valid0, valid1, entries): the lane's two rows; inside it
+  // entries(c0, c1) calls c0(j, a_ij, {r_j, p_j}) for row i0's entries and
+  // c1 for row i1's, each row in stored order.  rp must be readable at
+  // indices -1 and n (a lane's 16-byte gather may cover one pair past
+  // either end; those halves are never consumed).  row_of must be null.
+  // Slices of at most 7 entries: at most the 1536 blocks that fit at once
+  // at the pass's 6 waves per SIMD (measured at 256^3, FP16 values: 8 %
+  // faster than 4096 blocks); wider slices: 4096 (27-point 192^3: 3-5 %
+  // faster than 1536).
+  int grid_pairs(bool wide) const {
+    return grid_for((int64_t(n) + 1) / 2, wide ? kFinishOne : 1536);
+  }
+
+  template <int G, class C0, class C1>
+  __device__ __forceinline__ void pair_group(int64_t base, int32_t w, int32_t g, int half, int l2,
+                                             int64_t ka, int64_t kb, int32_t r0, int32_t standin,
+                                             const float2_t *rp, C0 &&c0, C1 &&c1) const {
+    // values of entries g .. g + G - 1 of both rows (row r0: v0, r0 + 1: v1)
+    V v0[G], v1[G];
+    constexpr int F = G / 4 * 4;
+#pragma unroll
+    for (int c = 0; 4 * c < F; ++c) {
+      V t[8];
+      ld_run<8>(val + base + 64 * int64_t(g + 4 * c) + 8 * l2, t);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v0[4 * c + k] = t[k];
+        v1[4 * c + k] = t[4 + k];
+      }
+    }
+    if constexpr (G - F >= 2) {
+      V t[4];
+      ld_run<4>(val + base + 64 * int64_t(g + F) + 4 * l2, t);
+      v0[F] = t[0];
+      v0[F + 1] = t[1];
+      v1[F] = t[2];
+      v1[F + 1] = t[3];
+    }
+    if constexpr ((G - F) % 2 == 1) {
+      V t[2];
+      ld_run<2>(val + base + 64 * int64_t(w - 1) + 2 * l2, t);
+      v0[G - 1] = t[0];
+      v1[G - 1] = t[1];
+    }
+    // the lane's slice's offsets and its two rows' entry bits
+    int32_t d[G];
+    uint32_t h0 = 0, h1 = 0;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int32_t oa = soff[ka + g + u], ob = soff[kb + g + u];
+      const uint64_t ma = smask[ka + g + u], mb = smask[kb + g + u];
+      d[u] = half ? ob : oa;
+      const uint64_t m = half ? mb : ma;
+      h0 |= uint32_t((m >> (2 * l2)) & 1u) << u;
+      h1 |= uint32_t((m >> (2 * l2 + 1)) & 1u) << u;
+    }
+    // one 16-byte gather per entry for both rows; an entry neither row has
+    // gathers at the slice's first row (not consumed)
+    float4_t x[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int32_t j = ((h0 | h1) >> u) & 1u ? r0 + d[u] : standin;
+      __builtin_memcpy(&x[u], rp + j, sizeof(float4_t));
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if ((h0 >> u) & 1u) c0(r0 + d[u], T(widen(v0[u])), float2_t{x[u].x, x[u].y});
+      if ((h1 >> u) & 1u) c1(r0 + 1 + d[u], T(widen(v1[u])), float2_t{x[u].z, x[u].w});
+    }
+  }
+
+  template <class Body>
+  __device__ __forceinline__ void walk_pairs(const float2_t *rp, Body &&body) const {
+    static_assert(OffOnly && sizeof(V) < 8, "two rows per lane: FP32/FP16 offset slices");
+    const int64_t ntiles = (int64_t(n) + 2 * kBlock - 1) / (2 * kBlock);
+    const Sched sc = my_tiles(ntiles);
+    const int lane = threadIdx.x & 63, half = lane >> 5, l2 = lane & 31;
+    const int32_t ns = (n + kSlice - 1) / kSlice;
+    auto fetch = [&](int32_t j) { return rp[j]; };
+    for (int64_t t = sc.begin; t < sc.end; t += sc.stride) {
+      const int32_t sa = __builtin_amdgcn_readfirstlane(int32_t(t) * (2 * kBlock / kSlice) +
+                                                        2 * (int32_t(threadIdx.x) >> 6));
+      const int32_t sb = sa + 1;
+      // slice bounds; a slice past the last one has width 0
+      const int32_t ca = min(sa, ns - 1), cb = min(sb, ns - 1);
+      const int64_t base_a = slice_base(sp[ca]), base_b = slice_base(sp[cb]);
+      const int32_t wa = sa < ns ? int32_t((slice_base(sp[ca + 1]) - base_a) >> 6) : 0;
+      const int32_t wb = sb < ns ? int32_t((slice_base(sp[cb + 1]) - base_b) >> 6) : 0;
+      if (wa == wb) {
+        const int32_t sh = half ? sb : sa;
+        const int32_t r0 = sh * kSlice + 2 * l2;
+        const int32_t standin = min(sh, ns - 1) * kSlice;
+        const int64_t base = half ? base_b : base_a;
+        const int64_t ka = base_a >> 6, kb = base_b >> 6;
+        auto entries = [&](auto &&c0, auto &&c1) {
+          auto grp = [&](auto G, int32_t g) {
+            pair_group<decltype(G)::value>(base, wa, g, half, l2, ka, kb, r0, standin, rp, c0, c1);
+          };
+          // groups of four entries (a group's sixteen bytes of gathers per
+          // entry keep its registers within reach of more waves per SIMD)
+          int32_t g = 0;
+          for (; g + 4 <= wa; g += 4) grp(std::integral_constant<int, 4>(), g);
+          switch (wa - g) {
+            case 1: grp(std::integral_constant<int, 1>(), g); break;
+            case 2: grp(std::integral_constant<int, 2>(), g); break;
+            case 3: grp(std::integral_constant<int, 3>(), g); break;
+            default: break;
+          }
+        };
+        body(r0, r0 + 1, r0 < n, r0 + 1 < n, entries);
+      } else {
+        // one row per lane: row 64 sa + l, then row 64 sb + l
+        const int32_t i0 = sa * kSlice + lane, i1 = sb * kSlice + lane;
+        auto entries = [&](auto &&c0, auto &&c1) {
+          walk<true>(base_a, wa, lane, i0 < n ? i0 : ca * kSlice, ca * kSlice, fetch, c0);
+          walk<true>(base_b, wb, lane, i1 < n ? i1 : cb * kSlice, cb * kSlice, fetch, c1);
+        };
+        body(i0, i1, i0 < n, i1 < n, entries);
+      }
+    }
   }
 
   // Entries g .. g + W - 1 of the lane's row in a slice of width w (g even):
@@ -232,6 +411,10 @@ struct SellOp {
     }
   }
 };
+
+// Operators whose refinement pass walks two rows per lane.
+template <class Op> struct PairWalk : std::false_type {};
+template <class V> struct PairWalk<SellOp<V, float, true>> : std::integral_constant<bool, sizeof(V) < 8> {};
 
 // ------------------------------------------------------------------ packing
 

@@ -562,8 +562,8 @@ def test_bicgstab_restart_paths(mode, tol):
 
 @pytest.mark.parametrize("kind", ["csr27", "sten27", "csr7", "csr7p", "csr27p"])
 @pytest.mark.parametrize("lowp", ["f32", "f16"])
-def test_ir_cg_matches_oracle(kind, lowp):
-    g = (24, 20, 18)
+@pytest.mark.parametrize("g", [(24, 20, 18), (23, 19, 17)])  # the second: a partial last slice
+def test_ir_cg_matches_oracle(kind, lowp, g):
     Acsr, A = _matrix(kind, g)
     xs, b = _system(Acsr, seed=1)
     lo = Acsr[2].astype(np.float32 if lowp == "f32" else np.float16)
