@@ -142,7 +142,7 @@ __device__ __forceinline__ void batch_block_reduce(DD (&v)[ND], int R) {
       DD o;
       o.hi = __shfl_xor(v[d].hi, off);
       o.lo = __shfl_xor(v[d].lo, off);
-      v[d] = dd_add(v[d], o);
+      v[d] = dd_cascade(v[d], o);
     }
   }
   if (lane < R) {
@@ -154,7 +154,7 @@ __device__ __forceinline__ void batch_block_reduce(DD (&v)[ND], int R) {
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       DD t = sm[d][0][threadIdx.x];
-      for (int j = 1; j < kWaves; ++j) t = dd_add(t, sm[d][j][threadIdx.x]);
+      for (int j = 1; j < kWaves; ++j) t = dd_cascade(t, sm[d][j][threadIdx.x]);
       v[d] = t;
     }
   }
@@ -448,8 +448,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
           for (int j = 0; j < kL; ++j) cv[u][j] = cn[u][j];
       }
     }
-    DD v[2] = {a.get(), DD{0.0, 0.0}};
-    batch_block_reduce<2>(v, R);
+    DD v[1] = {a.get()};
+    batch_block_reduce<1>(v, R);
     if (int(threadIdx.x) < R) V.part1[(int64_t(bk.b) * R + threadIdx.x) * 2] = v[0];
   }
 }
@@ -527,8 +527,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass2(BatchView V, double *__r
         a.add(ri, ri);
       }
     }
-    DD v[2] = {a.get(), DD{0.0, 0.0}};
-    batch_block_reduce<2>(v, R);
+    DD v[1] = {a.get()};
+    batch_block_reduce<1>(v, R);
     if (int(threadIdx.x) < R) V.part[(int64_t(it.w) * R + threadIdx.x) * 2] = v[0];
   }
 }

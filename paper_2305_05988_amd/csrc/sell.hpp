@@ -318,6 +318,7 @@ struct SellOp {
   __device__ __forceinline__ void group(int64_t base, int32_t w, int32_t g, int lane, int32_t row,
                                         int32_t standin, Fetch &&fetch, Consume &&consume) const {
     int32_t cj[W];
+    bool has[W];
     V vj[W];
 #pragma unroll
     for (int c = 0; 2 * c < W; ++c) {
@@ -352,15 +353,22 @@ struct SellOp {
         msk[u] = smask[k + u];
       }
 #pragma unroll
-      for (int u = 0; u < W; ++u) cj[u] = (msk[u] >> lane) & 1u ? row + offs[u] : -1;
+      for (int u = 0; u < W; ++u) cj[u] = row + offs[u];
+      // the wave-uniform mask is the lane condition itself (it becomes the
+      // exec mask; no per-lane bit test)
+#pragma unroll
+      for (int u = 0; u < W; ++u) has[u] = __builtin_amdgcn_inverse_ballot_w64(msk[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < W; ++u) has[u] = cj[u] >= 0;
     }
     // padding slots fetch a stand-in row (not consumed)
     decltype(fetch(0)) xj[W];
 #pragma unroll
-    for (int u = 0; u < W; ++u) xj[u] = fetch(cj[u] >= 0 ? cj[u] : standin);
+    for (int u = 0; u < W; ++u) xj[u] = fetch(has[u] ? cj[u] : standin);
 #pragma unroll
     for (int u = 0; u < W; ++u)
-      if (cj[u] >= 0) consume(cj[u], T(widen(vj[u])), xj[u]);
+      if (has[u]) consume(cj[u], T(widen(vj[u])), xj[u]);
   }
 
   template <bool Off, class Fetch, class Consume>
