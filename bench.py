@@ -580,7 +580,7 @@ def kernel_suite(its, inputs, iters=10):
         "n": n, "grid_spmv": (n + 255) // 256,
         "k_cg_pass1<SellOp<double": M + 3 * V, "k_cg_pass2<double>": 6 * V,
         "k_jacobi<SellOp<double": M + 3 * V,
-        "k_cg_pass1<SellOp<float": M32 + 3 * V32, "k_cg_pass1<SellOp<__half": M16 + 3 * V32,
+        "k_cg_pass1<SellOp<float": M32 + 3 * V32, "k_cg_pass1_pairs<SellOp<__half": M16 + 3 * V32,
         "k_cg_pass2_f32x2": 6 * V32, "k_residual<SellOp<double": M + 3 * V}
     del A, b
     torch.cuda.empty_cache()
@@ -623,8 +623,8 @@ def kernel_suite(its, inputs, iters=10):
     out["stencil27_192_packed"] = {
         "n": n2, "k_cg_pass1<SellOp<double": packed_matrix_bytes(A3, n2) + 3 * V3,
         "k_cg_pass2<double>": 6 * V3,
-        "k_cg_pass1<SellOp<float": packed_lowp_bytes(A3, n2, 4) + 3 * V3_32,
-        "k_cg_pass1<SellOp<__half": packed_lowp_bytes(A3, n2, 2) + 3 * V3_32,
+        "k_cg_pass1_pairs<SellOp<float": packed_lowp_bytes(A3, n2, 4) + 3 * V3_32,
+        "k_cg_pass1_pairs<SellOp<__half": packed_lowp_bytes(A3, n2, 2) + 3 * V3_32,
         "k_cg_pass2_f32x2": 6 * V3_32}
     del A3, b3
     torch.cuda.empty_cache()
