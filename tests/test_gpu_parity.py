@@ -581,6 +581,26 @@ def test_ir_cg_matches_oracle(kind, lowp, g):
     assert err <= 1e-8
 
 
+@pytest.mark.parametrize("lowp", ["f32", "f16"])
+@pytest.mark.parametrize("g", [(1, 1, 1), (2, 1, 1), (63, 1, 1), (65, 1, 1), (129, 1, 1),
+                               (200, 1, 1), (65, 3, 1), (70, 2, 3)])
+def test_ir_small_and_ragged_slices(lowp, g):
+    """The refinement on packed offset-slice matrices whose slices pair up
+    unevenly: one row, a lone partial slice, a last slice narrower than the
+    one it pairs with (the tile falls back to one row per lane), partial
+    slices inside a pair; iterates bit for bit."""
+    print(f"IR edge: {g} {lowp}", flush=True)
+    Acsr, A = _matrix("csr7p", g)
+    xs, b = _system(Acsr, seed=5)
+    lo = Acsr[2].astype(np.float32 if lowp == "f32" else np.float16)
+    ref, rr = oracle.ir_cg(Acsr, lo, b, rtol=1e-10, max_iter=500, inner_rtol=1e-4)
+    x, info = its().solve(A, dev(b), method="cg", rtol=1e-10, max_iter=500, inner_dtype=lowp,
+                          inner_rtol=1e-4)
+    assert rr.status == oracle.OK and info.status == "ok"
+    assert info.iters == rr.iters and info.inner_iters == rr.inner_iters
+    assert np.array_equal(host(x), ref)
+
+
 # ------------------------------------------------------- edge cases / status
 
 @pytest.mark.parametrize("method", ["jacobi", "sgs", "cg", "bicgstab", "cgnb"])
