@@ -358,17 +358,36 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
     const int64_t nxy = int64_t(nx) * ny;
     const double2_t *rs = rp + bk.off * R + r;  // (cell 0, rhs r) of this system
     const double *cf = V.coef + bk.off;          // coefficient o of cell c: cf[o ncell + c]
+    // The parts of this thread's addresses that do not change from plane to
+    // plane, formed once per brick: the in-plane cell of each halo value it
+    // loads (-1 outside the grid) and of each of its cells, and its cells'
+    // neighbour flags (bit 0 y-1, 1 x-1, 2 x+1, 3 y+1, 4 inside the grid).
+    int64_t hoff[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int v = t + u * kBlock, h = v / R;
+      const int32_t gx = bk.x0 - 1 + h % HX, gy = bk.y0 - 1 + h / HX;
+      const bool in = v < NV && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      hoff[u] = in ? gx + int64_t(nx) * gy : -1;
+    }
+    int64_t coff[CPT];
+    uint32_t nb[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int k = cl + u * C;
+      const int32_t gx = bk.x0 + k % TX, gy = bk.y0 + k / TX;
+      const bool inside = gx < nx && gy < ny;
+      coff[u] = inside ? gx + int64_t(nx) * gy : -1;
+      nb[u] = uint32_t(gy > 0) | uint32_t(gx > 0) << 1 | uint32_t(gx < nx - 1) << 2 |
+              uint32_t(gy < ny - 1) << 3 | uint32_t(inside) << 4;
+    }
     // loads are unconditional (halo cells outside the grid load cell 0,
     // never consumed) so a plane's loads stay in flight together
     double2_t hv[NR];
     auto issue = [&](int32_t z) {
+      const int64_t zo = nxy * z;
 #pragma unroll
-      for (int u = 0; u < NR; ++u) {
-        const int v = t + u * kBlock, h = v / R;
-        const int32_t gx = bk.x0 - 1 + h % HX, gy = bk.y0 - 1 + h / HX;
-        const bool in = v < NV && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        hv[u] = rs[(in ? gx + int64_t(nx) * gy + nxy * z : 0) * R];
-      }
+      for (int u = 0; u < NR; ++u) hv[u] = rs[(hoff[u] >= 0 ? hoff[u] + zo : 0) * R];
     };
     auto put = [&](int32_t z) {
       double *d = slot[z & 3];
@@ -377,17 +396,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
         if (t + u * kBlock < NV) d[t + u * kBlock] = value(hv[u]);
     };
     // this thread's cells of the tile: k = cl + u C
-    auto cell_of = [&](int u, int32_t &gx, int32_t &gy) {
-      const int k = cl + u * C;
-      gx = bk.x0 + k % TX;
-      gy = bk.y0 + k / TX;
-    };
     auto coefs = [&](int32_t z, double (&cv)[CPT][kL]) {
+      const int64_t zo = nxy * z;
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
-        int32_t gx, gy;
-        cell_of(u, gx, gy);
-        const int64_t cell = gx < nx && gy < ny ? gx + int64_t(nx) * gy + nxy * z : 0;
+        const int64_t cell = coff[u] >= 0 ? coff[u] + zo : 0;
 #pragma unroll
         for (int j = 0; j < kL; ++j) {
           const int o = r + j * R;
@@ -413,8 +426,6 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
       const double *pm = slot[(z - 1) & 3], *pc = slot[z & 3], *pp = slot[(z + 1) & 3];
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
-        int32_t gx, gy;
-        cell_of(u, gx, gy);
         const int k = cl + u * C;
         const int hc = ((k / TX) + 1) * HX + k % TX + 1;  // the cell in the halo tile
         double co[7];
@@ -429,13 +440,14 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
         const double xv[7] = {pm[hc * R + r],        pc[(hc - HX) * R + r], pc[(hc - 1) * R + r],
                               pc[hc * R + r],        pc[(hc + 1) * R + r],  pc[(hc + HX) * R + r],
                               pp[hc * R + r]};
-        const bool in[7] = {z > 0, gy > 0, gx > 0, true, gx < nx - 1, gy < ny - 1, z < nz - 1};
+        const bool in[7] = {z > 0, bool(nb[u] & 1u), bool(nb[u] & 2u), true, bool(nb[u] & 4u),
+                            bool(nb[u] & 8u), z < nz - 1};
         double acc = 0.0;
 #pragma unroll
         for (int o = 0; o < 7; ++o)
           if (in[o]) acc = fma(co[o], xv[o], acc);
-        if (gx < nx && gy < ny) {
-          st_nt(q + (bk.off + gx + int64_t(nx) * gy + nxy * z) * R + r, acc);
+        if (nb[u] & 16u) {
+          st_nt(q + (bk.off + coff[u] + nxy * z) * R + r, acc);
           a.add(xv[3], acc);
         }
       }
