@@ -89,19 +89,21 @@ __device__ __forceinline__ void brick_march(const BrickGeom &g, Issue &&issue, P
     const int32_t bx = int32_t(bi % g.nbx), by = int32_t((bi / g.nbx) % g.nby);
     const int32_t bz = int32_t(bi / (int64_t(g.nbx) * g.nby));
     const int32_t x0 = bx * kBrickTX, y0 = by * kBrickTY, z0 = bz * g.zb, z1 = min(nz, z0 + g.zb);
-    // point k of the halo tile of plane z: its row, or -1 outside the grid
-    auto tile_row = [&](int k, int32_t z) -> int32_t {
+    // the in-plane part of the row of each halo-tile point this thread
+    // loads (the same for every plane), or -1 outside the grid
+    int32_t pin[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = t + u * kBlock;
       const int32_t py = y0 - 1 + k / kBrickCols, px = x0 - 1 + k % kBrickCols;
-      if (k >= kBrickPlane || z < 0 || z >= nz || px < 0 || px >= nx || py < 0 || py >= ny) return -1;
-      return px + nx * py + nxy * z;
-    };
+      pin[u] = k < kBrickPlane && px >= 0 && px < nx && py >= 0 && py < ny ? px + nx * py : -1;
+    }
     Raw rv[kPer];
     auto load_plane = [&](int32_t z) {
+      // callers pass planes inside the grid
+      const int32_t zo = nxy * z;
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int32_t r = tile_row(t + u * kBlock, z);
-        rv[u] = issue(r >= 0 ? r : 0);
-      }
+      for (int u = 0; u < kPer; ++u) rv[u] = issue(pin[u] >= 0 ? pin[u] + zo : 0);
     };
     auto store_plane = [&](int32_t z) {
       const int slot = z & (kBrickSlots - 1);
