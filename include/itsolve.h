@@ -355,9 +355,10 @@ const char *its_last_error(void); /* message of this thread's last error */
    its_varcoef_create), each with nrhs right-hand sides, solved by FP64 CG per
    (system, right-hand side) and advanced together.  The paper's experiments
    solve one large system per run; the batch is this library's analogue of
-   choosing the task granularity (Section 4.2): an autotuner picks how many
-   z planes one brick of the SpMV pass covers, by timing that pass on the
-   first solve.  Each (system, rhs) follows exactly the arithmetic of the
+   choosing the task granularity (Section 4.2): on the first solve an
+   autotuner picks how many z planes one brick of the SpMV pass covers and
+   how many tiles one work item of the update passes covers, by timing each
+   pass over the candidates (4, 8, 16, 32 and 64 for both).  Each (system, rhs) follows exactly the arithmetic of the
    single-system CG (the same iterates, bit for bit) and stops on its own
    test; m = check_every iterations (default 64) are captured in one HIP
    graph that is replayed until every (system, rhs) has stopped.
@@ -370,7 +371,8 @@ typedef struct {
   int32_t status;          /* ITS_OK if every (system, rhs) converged, else
                               ITS_BREAKDOWN if any broke down, else
                               ITS_NOT_CONVERGED */
-  int32_t tiles_per_item;  /* work-item length of the update passes */
+  int32_t tiles_per_item;  /* tiles per work item of the update passes (the
+                              autotuner's choice, or the fixed one) */
   int32_t graph_iters;     /* m */
   int32_t planes_per_brick; /* z planes per brick of the SpMV pass (the
                                autotuner's choice, or the fixed one) */
@@ -393,9 +395,9 @@ int64_t its_batch_cells(const its_batch *B);
 /* Bytes of device workspace its_batch_solve needs (256-byte aligned). */
 size_t its_batch_workspace_size(const its_batch *B);
 /* Fixes the work schedule: tiles_per_item, the tiles of 256/nrhs cells one
-   work item of the update passes covers (0: the default, 16), and
-   planes_per_brick, the z planes one brick of the SpMV pass covers (0: the
-   autotuner chooses at the next solve).  Results do not depend on either
+   work item of the update passes covers, and planes_per_brick, the z planes
+   one brick of the SpMV pass covers (0 for either: the autotuner chooses it
+   at the next solve, and keeps its choice for later solves).  Results do not depend on either
    (the reductions round their exact sums).  ITS_E_INVALID for a null handle
    or a negative value.  Synchronises the handle's stream. */
 its_status its_batch_set_schedule(its_batch *B, int32_t tiles_per_item, int32_t planes_per_brick);

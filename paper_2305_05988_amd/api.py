@@ -449,8 +449,8 @@ class Batch:
 
     def set_schedule(self, tiles_per_item=0, planes_per_brick=0):
         """Fix the work-item length of the update passes (tiles of 256/nrhs
-        cells; 0: the default) and the z planes per brick of the SpMV pass
-        (0: chosen by the autotuner at the next solve)."""
+        cells) and the z planes per brick of the SpMV pass; 0 for either:
+        chosen by the autotuner at the next solve."""
         L.check(L.lib().its_batch_set_schedule(self._h, int(tiles_per_item), int(planes_per_brick)),
                 "its_batch_set_schedule")
 

@@ -28,9 +28,8 @@ struct its_batch {
   std::vector<BatchSys> sys;
   BatchSys *d_sys = nullptr;
   double *coef = nullptr;
-  // work items of the update passes (tiles per item, fixed) and bricks of
-  // the SpMV pass (planes per brick, chosen by the autotuner on the first
-  // solve unless fixed)
+  // work items of the update passes (tiles per item) and bricks of the SpMV
+  // pass (planes per brick); 0 until the autotuner chooses at the next solve
   int32_t chunk = 0;
   std::vector<BatchItem> items;
   BatchItem *d_items = nullptr;
@@ -51,7 +50,7 @@ struct its_batch {
 
 namespace {
 
-constexpr int kDefaultTiles = 16;
+constexpr int kTuneTiles[] = {4, 8, 16, 32, 64};
 constexpr int kTunePlanes[] = {4, 8, 16, 32, 64};
 
 int cells_per_tile(int R) { return kBlock / R; }
@@ -206,49 +205,106 @@ __global__ void k_batch_fill_run(int32_t *run, int n) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) run[i] = 1;
 }
 
-// Autotuner: times the SpMV pass (the pass that dominates an iteration) for
-// each candidate brick length in z and keeps the fastest.  The pass only
-// writes q and the brick partials, which the iterations overwrite.
-its_status autotune(its_batch *B, char *ws, const BatchWs &L) {
+// State for timing the passes: every (system, rhs) running at an even
+// iteration past the first, alpha = beta = 0, so the update pass reads and
+// writes the pairs and q but leaves x alone.
+__global__ void k_batch_tune_state(BatchView V) {
+  const int64_t m = int64_t(V.nsys) * V.nrhs;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < m; i += int64_t(gridDim.x) * kBlock) {
+    BatchCg &c = V.st[i];
+    c.k = 2;
+    c.flag = kRunning;
+    c.alpha = c.beta = c.alpha_x = 0.0;
+  }
+}
+
+// Autotuner, run at the first solve for whichever of the two lengths is not
+// fixed.  The two passes of an iteration depend on one length each (the SpMV
+// pass on the bricks' planes, the update pass on the items' tiles), so the
+// best pair is the pair of per-pass bests: each candidate is timed over three
+// launches of its pass and the fastest kept.  The SpMV pass writes q and the
+// brick partials only; the update pass, at the state above, writes the pairs
+// and the item partials only; the prologue of the solve overwrites all four.
+its_status autotune(its_batch *B, char *ws, const BatchWs &L, double *x) {
   hipStream_t s = B->stream;
-  double best = 1e300;
-  int best_zb = kTunePlanes[0];
   hipEvent_t a, b;
   BHIP(hipEventCreate(&a));
   BHIP(hipEventCreate(&b));
   const auto t0 = std::chrono::steady_clock::now();
   its_status rs = ITS_OK;
-  for (int zb : kTunePlanes) {
-    build_bricks(B, zb);
-    if (int64_t(B->bricks.size()) > B->brick_cap) continue;
-    if ((rs = upload_schedule(B, s)) != ITS_OK) break;
-    BatchView V = view_of(B, ws, L);
-    const int G = pass_grid(int32_t(B->bricks.size()));
-    auto *pairs = reinterpret_cast<const double2_t *>(ws + L.pairs);
-    auto *q = reinterpret_cast<double *>(ws + L.q);
+  auto *pairs = reinterpret_cast<double2_t *>(ws + L.pairs);
+  auto *q = reinterpret_cast<double *>(ws + L.q);
+  // times three launches after one warm-up; negative on failure
+  auto timed = [&](auto &&launch) -> float {
+    launch();
+    (void)hipEventRecord(a, s);
+    for (int rep = 0; rep < 3; ++rep) launch();
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  };
+  auto prepare = [&](const BatchView &V) {
+    hipLaunchKernelGGL(k_batch_tune_state, dim3(std::min(1024, (B->nsys * B->nrhs + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, V);
     hipLaunchKernelGGL(k_batch_fill_run, dim3(std::max(1, (B->nsys + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        V.sys_run, B->nsys);
     launch_compact(s, V);
-    launch_pass1(G, s, V, pairs, q);  // warm-up
-    (void)hipEventRecord(a, s);
-    for (int rep = 0; rep < 3; ++rep) launch_pass1(G, s, V, pairs, q);
-    (void)hipEventRecord(b, s);
-    if (hipEventSynchronize(b) != hipSuccess) {
-      rs = its_fail(ITS_E_HIP, "autotune timing");
-      break;
+  };
+  const bool tune_planes = B->zb == 0, tune_tiles = B->chunk == 0;
+  if (tune_planes) {
+    float best = 1e30f;
+    int best_zb = kTunePlanes[0];
+    for (int zb : kTunePlanes) {
+      build_bricks(B, zb);
+      if (int64_t(B->bricks.size()) > B->brick_cap) continue;
+      if ((rs = upload_schedule(B, s)) != ITS_OK) break;
+      const BatchView V = view_of(B, ws, L);
+      const int G = pass_grid(int32_t(B->bricks.size()));
+      prepare(V);
+      const float ms = timed([&] { launch_pass1(G, s, V, pairs, q); });
+      if (ms < 0.f) {
+        rs = its_fail(ITS_E_HIP, "autotune timing");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_zb = zb;
+      }
     }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, a, b);
-    if (ms < best) {
-      best = ms;
-      best_zb = zb;
+    if (rs == ITS_OK) {
+      B->zb = best_zb;
+      build_bricks(B, best_zb);
+    }
+  }
+  if (rs == ITS_OK && tune_tiles) {
+    float best = 1e30f;
+    int best_chunk = kTuneTiles[0];
+    for (int chunk : kTuneTiles) {
+      build_items(B, chunk);
+      if ((rs = upload_schedule(B, s)) != ITS_OK) break;
+      const BatchView V = view_of(B, ws, L);
+      const int G = pass_grid(V.nitems);
+      prepare(V);
+      const float ms = timed([&] { launch_pass2(G, s, V, x, pairs, q); });
+      if (ms < 0.f) {
+        rs = its_fail(ITS_E_HIP, "autotune timing");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_chunk = chunk;
+      }
+    }
+    if (rs == ITS_OK) {
+      B->chunk = best_chunk;
+      build_items(B, best_chunk);
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rs != ITS_OK) return rs;
-  B->zb = best_zb;
-  build_bricks(B, best_zb);
   B->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return upload_schedule(B, s);
 }
@@ -325,9 +381,8 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
       rs = its_fail(ITS_E_HIP, "device allocation failed");
       break;
     }
-    B->chunk = kDefaultTiles;
-    build_items(B, B->chunk);
-    build_bricks(B, kTunePlanes[0]);  // replaced by the autotuner's choice
+    build_items(B, kTuneTiles[0]);    // both replaced by the autotuner's choice
+    build_bricks(B, kTunePlanes[0]);
     // the coefficients are formed on the caller's stream, after k is ready
     hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(B->d_sys, B->sys.data(), sizeof(BatchSys) * size_t(nsys), hipMemcpyHostToDevice, cs) != hipSuccess) {
@@ -376,13 +431,13 @@ its_status its_batch_set_schedule(its_batch *B, int32_t tiles_per_item, int32_t 
   if (tiles_per_item < 0 || planes_per_brick < 0)
     return its_fail(ITS_E_INVALID, "tiles_per_item and planes_per_brick must be >= 0");
   drop_graph(B);
-  B->chunk = tiles_per_item > 0 ? tiles_per_item : kDefaultTiles;
-  build_items(B, B->chunk);
+  B->chunk = tiles_per_item;
   B->zb = planes_per_brick;
   B->tune_ms = 0.0;
+  if (tiles_per_item > 0) build_items(B, tiles_per_item);
   if (planes_per_brick > 0) build_bricks(B, planes_per_brick);
-  // the device copy of the systems carries both ranges; an autotuned brick
-  // list is uploaded by the tuner
+  // the device copy of the systems carries both ranges; autotuned lists are
+  // uploaded by the tuner
   return upload_schedule(B, B->stream);
 }
 
@@ -405,8 +460,8 @@ its_status its_batch_solve(its_batch *B, const its_options *o, const double *b, 
   // order the solve after the caller's work
   BHIP(hipEventRecord(B->ev, cs));
   BHIP(hipStreamWaitEvent(s, B->ev, 0));
-  if (B->zb == 0) {
-    its_status rs = autotune(B, ws, L);
+  if (B->zb == 0 || B->chunk == 0) {
+    its_status rs = autotune(B, ws, L, x);
     if (rs != ITS_OK) return rs;
   }
   BatchView V = view_of(B, ws, L);

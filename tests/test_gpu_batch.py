@@ -117,9 +117,19 @@ def test_batch_autotuner_reports_its_choice():
     dims, kc, b, B = _batch(4, 8, lo=8, hi=16, seed=18)
     x, info = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
     assert info.planes_per_brick in (4, 8, 16, 32, 64) and info.tune_ms > 0
-    assert info.tiles_per_item == 16 and info.graph_iters == 64
+    assert info.tiles_per_item in (4, 8, 16, 32, 64) and info.graph_iters == 64
     x, info2 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
     assert info2.planes_per_brick == info.planes_per_brick and info2.tune_ms == info.tune_ms
+    assert info2.tiles_per_item == info.tiles_per_item
+    # one length fixed, the other tuned
+    B.set_schedule(3, 0)
+    x3, info3 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
+    assert info3.tiles_per_item == 3 and info3.planes_per_brick in (4, 8, 16, 32, 64) and info3.tune_ms > 0
+    B.set_schedule(0, 5)
+    x4, info4 = B.solve(dev(b.ravel()), rtol=1e-8, max_iter=2000)
+    assert info4.planes_per_brick == 5 and info4.tiles_per_item in (4, 8, 16, 32, 64) and info4.tune_ms > 0
+    assert np.array_equal(host(x3), host(x)) and np.array_equal(host(x4), host(x))
+    assert np.array_equal(info3.iters, info.iters) and np.array_equal(info4.iters, info.iters)
 
 
 def _explicit(dims, nrhs, seed):
