@@ -13,7 +13,7 @@ the library on their workloads.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras] [--no-cpu]
                     [--layout packed|csr]
-    python bench.py --extra-only batched|small32|differentiation|paper_counts
+    python bench.py --extra-only batched|small32|differentiation|paper_counts|kernels|footprint
 
 paper_counts is not part of the default run: it reproduces the paper's
 one-node iteration counts (Sec. 4.1) for candidate readings of its matrix.
@@ -157,10 +157,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: one 1 GiB stream copy first (HBM counter calibration)")
     ap.add_argument("--extra-only",
-                    choices=("batched", "small32", "differentiation", "paper_counts", "kernels"),
+                    choices=("batched", "small32", "differentiation", "paper_counts", "kernels",
+                             "footprint"),
                     help="profiling: run only this secondary workload and print its figures "
                          "(kernels: a few fixed iterations of every benchmark workload, one "
-                         "after the other, with each kernel's bytes per launch)")
+                         "after the other, with each kernel's bytes per launch; footprint: "
+                         "streaming rates below and above the 256 MB Infinity Cache)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver "
@@ -186,7 +188,7 @@ def main():
         del src, dst
     if args.extra_only:
         fn = {"batched": batched, "small32": small32, "differentiation": differentiation,
-              "paper_counts": paper_counts, "kernels": kernel_suite}
+              "paper_counts": paper_counts, "kernels": kernel_suite, "footprint": footprint}
         print(json.dumps({args.extra_only: fn[args.extra_only](its, inputs)}), flush=True)
         return
     N = args.n
@@ -628,6 +630,45 @@ def kernel_suite(its, inputs, iters=10):
         "k_cg_pass2_f32x2": 6 * V3_32}
     del A3, b3
     torch.cuda.empty_cache()
+    return out
+
+
+def footprint(its, inputs, iters=10):
+    """Streaming rate against working-set size.  MI355X keeps a 256 MB
+    memory-side Infinity Cache in front of HBM, so a pass whose vectors were
+    just written by the previous pass can stream faster than HBM alone allows
+    while they fit.  Measured: the stream copy (footprint 2x the bytes
+    copied), and the single-system CG passes on the matrix-free 7-point
+    stencil at 256^3 (16.8M rows: 0.5 GB of vectors) and at 640 x 640 x 670
+    (274M rows: about the 512 x 8 batch's 275.5M values), fixed iterations.
+    The wall-clock rates printed here include launch gaps (they dominate the
+    small copies); per-launch durations come from a rocprofv3 kernel trace
+    of this leg (the copies run in ascending size, 21 launches each)."""
+    import torch
+    out = {"copy_gbs": {}}
+    for mib in (32, 64, 128, 256, 512, 1024, 4096):
+        src = torch.ones(mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        its.stream_copy(src, dst)
+        t, _ = timed(lambda: its.stream_copy(src, dst), reps=20)
+        out["copy_gbs"][f"{mib}MiB"] = 2 * src.numel() * 8 / t / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+    log(f"footprint: copy {json.dumps(out['copy_gbs'])}")
+    for dims in ((256, 256, 256), (640, 640, 670)):
+        S = its.StencilMatrix(*dims, inputs.POISSON7)
+        n = S.n
+        b = torch.ones(n, dtype=torch.float64, device="cuda")
+        its.solve(S, b, method="cg", rtol=0.0, max_iter=iters)
+        t, (x, info) = timed(lambda: its.solve(S, b, method="cg", rtol=0.0, max_iter=iters))
+        key = "x".join(str(d) for d in dims)
+        # pass 1 moves 3V (the {r, p} pairs and q), pass 2 5V on even and 7V
+        # on odd iterations (x every other one)
+        out[key] = {"n": n, "iters": info.iters, "s": t, "ms_per_iter": t / info.iters * 1e3,
+                    "bytes_per_iter": 9 * 8 * n, "gbs": info.iters * 9 * 8 * n / t / 1e9}
+        log(f"footprint: stencil cg {key}: {json.dumps(out[key])}")
+        del S, b, x
+        torch.cuda.empty_cache()
     return out
 
 
