@@ -422,9 +422,10 @@ def batched(its, inputs, nsys=512, nrhs=8):
     it = info.iters
     # bytes actually needed: per (system, rhs) iteration 9 vector touches of 8 B per cell on
     # average (x is read and written every other iteration);
-    # per system iteration the 7 coefficients (56 B per cell) once for all right-hand sides
+    # per system iteration the operator once for all right-hand sides: the diagonal and the
+    # three upper face coefficients (32 B per cell; a lower face is the neighbour's upper one)
     vec_bytes = float(np.sum(it * n_s[:, None]) * 72)
-    coef_bytes = float(np.sum(it.max(axis=1) * n_s) * 56)
+    coef_bytes = float(np.sum(it.max(axis=1) * n_s) * 32)
     out = {"systems": nsys, "rhs": nrhs, "cells": int(n_s.sum()), "setup_s": setup,
            "status": info.status, "solve_s": dt, "first_solve_s": first.solve_ms / 1e3,
            "tune_ms": first.tune_ms, "tiles_per_item": info.tiles_per_item,

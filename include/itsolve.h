@@ -384,8 +384,10 @@ typedef struct {
 
 /* dims: host, 3 * nsys values (nx, ny, nz per system, each >= 1).  k: device,
    the systems' per-cell coefficients concatenated (positive, finite); read
-   once here to form each cell's 7 coefficients (same roundings as
-   its_varcoef_create) into memory the handle owns, so k may be freed after.
+   once here to form each cell's diagonal and upper face coefficients (same
+   roundings as its_varcoef_create; a lower face's coefficient is the
+   neighbour's upper one, 32 bytes per cell in all) into memory the handle
+   owns, so k may be freed after.
    nrhs: 1, 2, 4 or 8.  Synchronises `stream`. */
 its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, int32_t nrhs,
                             void *stream, its_batch **out /* host, out */);

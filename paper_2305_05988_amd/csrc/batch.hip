@@ -377,7 +377,7 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
     if (hipMalloc(&B->d_sys, sizeof(BatchSys) * size_t(nsys)) != hipSuccess ||
         hipMalloc(&B->d_items, sizeof(BatchItem) * size_t(B->item_cap)) != hipSuccess ||
         hipMalloc(&B->d_bricks, sizeof(BatchBrick) * size_t(B->brick_cap)) != hipSuccess ||
-        hipMalloc(&B->coef, sizeof(double) * 7 * size_t(off)) != hipSuccess) {
+        hipMalloc(&B->coef, sizeof(double) * kCoefs * size_t(off)) != hipSuccess) {
       rs = its_fail(ITS_E_HIP, "device allocation failed");
       break;
     }

@@ -10,10 +10,15 @@ namespace its {
 // [off_s, off_s + n_s), rows numbered i + nx(j + ny k) inside it).  Vectors
 // interleave the right-hand sides: value (cell g, rhs r) sits at g R + r, so
 // a block's 256 threads cover 256/R consecutive cells x R right-hand sides
-// and every access is coalesced.  The operator is stored once per cell as
-// its 7 coefficients in chain order (z-1, y-1, x-1, diagonal, x+1, y+1, z+1;
-// 0 outside the grid), coef[o * ncell + g], and reused by all R right-hand
-// sides.  The SpMV pass works on bricks (an x-y tile of a system marched
+// and every access is coalesced.  The operator is stored once per cell and
+// reused by all R right-hand sides: its diagonal and its three upper face
+// coefficients (x+1, y+1, z+1; 0 outside the grid), coef[a * ncell + g] for
+// a = 0 (diagonal), 1 (x+1), 2 (y+1), 3 (z+1).  A lower face's coefficient
+// is the upper one of the neighbour across it, the same value bit for bit
+// (the harmonic mean 2 k k' / (k + k') of the two cells, formed from the
+// same operands in either order), so 32 bytes per cell hold the operator's
+// 7 coefficients in chain order (z-1, y-1, x-1, diagonal, x+1, y+1, z+1):
+// coef_at(o) below.  The SpMV pass works on bricks (an x-y tile of a system marched
 // through a run of z planes), the other passes on work items (runs of
 // 256/R-cell tiles inside one system); each brick or item leaves one
 // double-double partial per right-hand side, and one block per system
@@ -94,6 +99,12 @@ __device__ __forceinline__ void batch_coords(const BatchSys &sy, int64_t lc, int
 // Per-cell coefficients of the variable-coefficient operator (the roundings
 // of VarCoefOp: harmonic faces ((2 a) b) / (a + b) with a the lower row,
 // boundary face = the cell's k, diagonal summed from 0 in face order).
+// Where coefficient o of the chain (z-1, y-1, x-1, diagonal, x+1, y+1, z+1)
+// of a cell is stored: array kCoefArray[o], at the cell itself or, for a
+// lower face, at the neighbour across it (cell - nxy, - nx, - 1).
+constexpr int kCoefs = 4;
+constexpr int kCoefArray[7] = {3, 2, 1, 0, 1, 2, 3};
+
 __global__ void __launch_bounds__(kBlock) k_batch_coef(BatchView V, const double *__restrict__ k,
                                                        double *__restrict__ coef) {
   for (int32_t s = blockIdx.x; s < V.nsys; s += gridDim.x) {
@@ -118,14 +129,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_coef(BatchView V, const double
         }
         diag = diag + f[o];
       }
+      // the lower faces' values are the lower neighbours' upper ones
       const int64_t N = V.ncell;
-      coef[0 * N + g] = in[0] ? -f[0] : 0.0;
-      coef[1 * N + g] = in[1] ? -f[1] : 0.0;
-      coef[2 * N + g] = in[2] ? -f[2] : 0.0;
-      coef[3 * N + g] = diag;
-      coef[4 * N + g] = in[3] ? -f[3] : 0.0;
-      coef[5 * N + g] = in[4] ? -f[4] : 0.0;
-      coef[6 * N + g] = in[5] ? -f[5] : 0.0;
+      coef[0 * N + g] = diag;
+      coef[1 * N + g] = in[3] ? -f[3] : 0.0;
+      coef[2 * N + g] = in[4] ? -f[4] : 0.0;
+      coef[3 * N + g] = in[5] ? -f[5] : 0.0;
     }
   }
 }
@@ -179,7 +188,7 @@ __device__ __forceinline__ double batch_row(const BatchView &V, const BatchSys &
   for (int o = 0; o < 7; ++o) raw[o] = load((in[o] ? g + off[o] : g) * V.nrhs + r);
   double a[7];
 #pragma unroll
-  for (int o = 0; o < 7; ++o) a[o] = V.coef[o * V.ncell + g];
+  for (int o = 0; o < 7; ++o) a[o] = V.coef[kCoefArray[o] * V.ncell + (o < 3 && in[o] ? g + off[o] : g)];
   double acc = 0.0;
 #pragma unroll
   for (int o = 0; o < 7; ++o) {
@@ -314,8 +323,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_zero(BatchView V, double *__re
 // LDS while plane z+2 is in flight.  Every neighbour of a row then comes from
 // LDS, and each value is read from memory once per brick plus its halo.  The
 // 7 coefficients of a cell are read once by the R lanes that share it (lane
-// r takes coefficients r, r + R, ...), one plane ahead, and passed between
-// those lanes.  The chain is the single-system one.
+// r takes coefficients r, r + R, ...; a lower face's from the neighbour's
+// upper face, whose line the neighbouring cell or the previous plane already
+// brought in), one plane ahead, and passed between those lanes.  The chain
+// is the single-system one.
 template <int R>
 struct BrickShape;
 template <>
@@ -395,16 +406,33 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
       for (int u = 0; u < NR; ++u)
         if (t + u * kBlock < NV) d[t + u * kBlock] = value(hv[u]);
     };
-    // this thread's cells of the tile: k = cl + u C
+    // this thread's cells of the tile: k = cl + u C.  Lane r's coefficient
+    // j is chain entry o = r + j R (entries past 6 load the diagonal, never
+    // used): array kCoefArray[o], and for a lower face the neighbour's cell
+    // when that neighbour exists (its flag: z > 0, nb bit 0 or bit 1).
+    const double *ca[kL];
+#pragma unroll
+    for (int j = 0; j < kL; ++j) {
+      const int o = r + j * R;
+      ca[j] = cf + int64_t(o < 7 ? kCoefArray[o] : 0) * V.ncell;
+    }
     auto coefs = [&](int32_t z, double (&cv)[CPT][kL]) {
       const int64_t zo = nxy * z;
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
-        const int64_t cell = coff[u] >= 0 ? coff[u] + zo : 0;
+        const int64_t cell = coff[u] >= 0 ? int64_t(coff[u]) + zo : 0;
 #pragma unroll
         for (int j = 0; j < kL; ++j) {
-          const int o = r + j * R;
-          cv[u][j] = cf[int64_t(o < 7 ? o : 6) * V.ncell + cell];
+          int64_t at = cell;
+          if (j * R < 3) {  // lower faces occur only among the first entries
+            const int o = r + j * R;
+            if (coff[u] >= 0) {
+              if (o == 0 && z > 0) at -= nxy;
+              if (o == 1 && (nb[u] & 1u)) at -= nx;
+              if (o == 2 && (nb[u] & 2u)) at -= 1;
+            }
+          }
+          cv[u][j] = ca[j][at];
         }
       }
     };
