@@ -388,7 +388,9 @@ typedef struct {
    roundings as its_varcoef_create; a lower face's coefficient is the
    neighbour's upper one, 32 bytes per cell in all) into memory the handle
    owns, so k may be freed after.
-   nrhs: 1, 2, 4 or 8.  Synchronises `stream`. */
+   nrhs: 1, 2, 4 or 8 (else ITS_E_UNSUPPORTED; so is a system with nx * ny
+   >= 2^31, a batch of 2^40 or more values, or one of 2^30 or more tiles or
+   one-plane bricks).  Synchronises `stream`. */
 its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, int32_t nrhs,
                             void *stream, its_batch **out /* host, out */);
 its_status its_batch_destroy(its_batch *B);

@@ -338,6 +338,10 @@ its_status its_batch_create(int32_t nsys, const int32_t *dims, const double *k, 
       delete B;
       return its_fail(ITS_E_INVALID, "system " + std::to_string(s) + " has an empty grid");
     }
+    if (int64_t(nx) * ny >= (int64_t(1) << 31)) {
+      delete B;
+      return its_fail(ITS_E_UNSUPPORTED, "system " + std::to_string(s) + " has 2^31 or more cells per plane");
+    }
     BatchSys sy{};
     sy.off = off;
     sy.nx = nx;

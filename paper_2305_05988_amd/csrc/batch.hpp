@@ -373,22 +373,22 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
     // plane, formed once per brick: the in-plane cell of each halo value it
     // loads (-1 outside the grid) and of each of its cells, and its cells'
     // neighbour flags (bit 0 y-1, 1 x-1, 2 x+1, 3 y+1, 4 inside the grid).
-    int64_t hoff[NR];
+    int32_t hoff[NR];
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
       const int v = t + u * kBlock, h = v / R;
       const int32_t gx = bk.x0 - 1 + h % HX, gy = bk.y0 - 1 + h / HX;
       const bool in = v < NV && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-      hoff[u] = in ? gx + int64_t(nx) * gy : -1;
+      hoff[u] = in ? gx + nx * gy : -1;  // a plane has fewer than 2^31 cells
     }
-    int64_t coff[CPT];
+    int32_t coff[CPT];
     uint32_t nb[CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
       const int k = cl + u * C;
       const int32_t gx = bk.x0 + k % TX, gy = bk.y0 + k / TX;
       const bool inside = gx < nx && gy < ny;
-      coff[u] = inside ? gx + int64_t(nx) * gy : -1;
+      coff[u] = inside ? gx + nx * gy : -1;
       nb[u] = uint32_t(gy > 0) | uint32_t(gx > 0) << 1 | uint32_t(gx < nx - 1) << 2 |
               uint32_t(gy < ny - 1) << 3 | uint32_t(inside) << 4;
     }
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
     auto issue = [&](int32_t z) {
       const int64_t zo = nxy * z;
 #pragma unroll
-      for (int u = 0; u < NR; ++u) hv[u] = rs[(hoff[u] >= 0 ? hoff[u] + zo : 0) * R];
+      for (int u = 0; u < NR; ++u) hv[u] = rs[(hoff[u] >= 0 ? int64_t(hoff[u]) + zo : 0) * R];
     };
     auto put = [&](int32_t z) {
       double *d = slot[z & 3];
@@ -416,6 +416,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
       const int o = r + j * R;
       ca[j] = cf + int64_t(o < 7 ? kCoefArray[o] : 0) * V.ncell;
     }
+    // lower faces are the chain entries o = r + j R < 3, so only the first
+    // kLow entries of a lane can be one; such an entry is read at the
+    // neighbour across the face (a plane back for z-1, where z > 0; a row
+    // back for y-1 and a cell back for x-1, where the cell's flags have them)
+    constexpr int kLow = R == 1 ? 3 : R == 2 ? 2 : 1;
     auto coefs = [&](int32_t z, double (&cv)[CPT][kL]) {
       const int64_t zo = nxy * z;
 #pragma unroll
@@ -424,13 +429,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
 #pragma unroll
         for (int j = 0; j < kL; ++j) {
           int64_t at = cell;
-          if (j * R < 3) {  // lower faces occur only among the first entries
+          if (j < kLow && coff[u] >= 0) {
             const int o = r + j * R;
-            if (coff[u] >= 0) {
-              if (o == 0 && z > 0) at -= nxy;
-              if (o == 1 && (nb[u] & 1u)) at -= nx;
-              if (o == 2 && (nb[u] & 2u)) at -= 1;
-            }
+            at -= o == 0 ? (z > 0 ? nxy : 0)
+                         : o == 1 ? ((nb[u] & 1u) ? nx : 0) : o == 2 ? ((nb[u] & 2u) ? 1 : 0) : 0;
           }
           cv[u][j] = ca[j][at];
         }
@@ -475,7 +477,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
         for (int o = 0; o < 7; ++o)
           if (in[o]) acc = fma(co[o], xv[o], acc);
         if (nb[u] & 16u) {
-          st_nt(q + (bk.off + coff[u] + nxy * z) * R + r, acc);
+          st_nt(q + (bk.off + int64_t(coff[u]) + nxy * z) * R + r, acc);
           a.add(xv[3], acc);
         }
       }

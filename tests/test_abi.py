@@ -89,6 +89,11 @@ def test_host_side_argument_errors(lib):
     bad_dims = (C.c_int32 * 3)(4, 0, 4)
     assert lib.its_batch_create(1, bad_dims, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
     assert lib.its_batch_create(0, dims, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
+    # the SpMV pass keeps in-plane offsets in 32 bits: 2^31 cells per plane are refused
+    wide = (C.c_int32 * 3)(1 << 16, 1 << 15, 1)
+    assert lib.its_batch_create(1, wide, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_UNSUPPORTED
+    wide_ok = (C.c_int32 * 3)(1 << 16, (1 << 15) - 1, 0)  # fits, but empty: rejected as invalid
+    assert lib.its_batch_create(1, wide_ok, C.c_void_p(8), 4, P0, C.byref(h)) == L.ITS_E_INVALID
     assert lib.its_batch_cells(P0) == -1 and lib.its_batch_workspace_size(P0) == 0
     assert lib.its_batch_set_schedule(P0, 4, 0) == L.ITS_E_INVALID
     assert lib.its_csr_transpose(P0, P0) == L.ITS_E_INVALID
