@@ -40,7 +40,8 @@ class _Matrix:
     _h = None
 
     def __del__(self):
-        if self._h is not None and L._lib is not None:
+        # at interpreter exit the module globals may already be gone
+        if self._h is not None and L is not None and L._lib is not None:
             L._lib.its_matrix_destroy(self._h)
             self._h = None
 
@@ -438,7 +439,7 @@ class Batch:
         self._ws = None
 
     def __del__(self):
-        if getattr(self, "_h", None) is not None and L._lib is not None:
+        if getattr(self, "_h", None) is not None and L is not None and L._lib is not None:
             L._lib.its_batch_destroy(self._h)
             self._h = None
 
