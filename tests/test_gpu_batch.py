@@ -144,20 +144,21 @@ def _explicit(dims, nrhs, seed):
 # The SpMV pass marches bricks of TX x TY cells (R = 8: 16 x 4, 4: 32 x 4,
 # 2: 32 x 8, 1: 64 x 8) through runs of z planes.  Grids one cell short of,
 # equal to and one past a tile edge, a single cell, and z runs of 1, 2, 3
-# and whole columns; work items of 1, 3 and 16 tiles for the update passes.
+# and whole columns; work items of 1, 3 and 16 tiles for the update passes;
+# (0, 0): both lengths chosen by the autotuner.
 @pytest.mark.parametrize("nrhs,dims", [
     (8, [(16, 4, 3), (17, 5, 2), (15, 3, 7), (1, 1, 1), (33, 9, 4)]),
     (4, [(32, 4, 2), (33, 5, 3), (31, 3, 5), (3, 9, 2)]),
     (2, [(32, 8, 3), (33, 9, 2), (1, 1, 1), (5, 17, 4)]),
     (1, [(64, 8, 2), (65, 9, 1), (63, 7, 3), (2, 3, 40)]),
 ])
-@pytest.mark.parametrize("tiles,planes", [(1, 1), (3, 2), (16, 3), (16, 0)])
+@pytest.mark.parametrize("tiles,planes", [(1, 1), (3, 2), (16, 3), (16, 0), (0, 0)])
 def test_batch_bricks_bit_exact(nrhs, dims, tiles, planes):
     k = 5
     dims, kc, b, B = _explicit(dims, nrhs, seed=19)
     B.set_schedule(tiles, planes)
     x, info = B.solve(dev(b.ravel()), rtol=0.0, max_iter=k)
-    assert info.tiles_per_item == tiles
+    assert info.tiles_per_item == tiles if tiles else info.tiles_per_item in (4, 8, 16, 32, 64)
     if planes:
         assert info.planes_per_brick == planes and info.tune_ms == 0.0
     ref = _oracle_each(dims, kc, b, lambda A, bb: oracle.cg(A, bb, rtol=0.0, max_iter=k)[0])
