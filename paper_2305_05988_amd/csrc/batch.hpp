@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_pass1(BatchView V, const doubl
     const int32_t nx = bk.nx, ny = bk.ny, nz = bk.nz;
     const int64_t nxy = int64_t(nx) * ny;
     const double2_t *rs = rp + bk.off * R + r;  // (cell 0, rhs r) of this system
-    const double *cf = V.coef + bk.off;          // coefficient o of cell c: cf[o ncell + c]
+    const double *cf = V.coef + bk.off;          // array a of cell c: cf[a ncell + c]
     // The parts of this thread's addresses that do not change from plane to
     // plane, formed once per brick: the in-plane cell of each halo value it
     // loads (-1 outside the grid) and of each of its cells, and its cells'
