@@ -227,9 +227,11 @@ __global__ void k_batch_tune_state(BatchView V) {
 // and the item partials only; the prologue of the solve overwrites all four.
 its_status autotune(its_batch *B, char *ws, const BatchWs &L, double *x) {
   hipStream_t s = B->stream;
-  hipEvent_t a, b;
-  BHIP(hipEventCreate(&a));
-  BHIP(hipEventCreate(&b));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return its_fail(ITS_E_HIP, "autotune events");
+  }
   const auto t0 = std::chrono::steady_clock::now();
   its_status rs = ITS_OK;
   auto *pairs = reinterpret_cast<double2_t *>(ws + L.pairs);
