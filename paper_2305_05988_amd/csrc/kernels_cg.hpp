@@ -116,16 +116,45 @@ struct FinCg1 {
   }
 };
 
+// pq, pq_count: when pq is not null, the SpMV pass's p.q partials (first- or
+// second-level, a few hundred at most), which every block reduces itself in
+// the finishing kernel's order (finish_in_block) and turns into alpha as
+// FinCg1 does -- block 0 records alpha, or the breakdown, in the State -- so
+// no finishing kernel runs between the two passes.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x,
                                                      typename Pair<T>::type *__restrict__ rp,
-                                                     const T *__restrict__ q, const State *st,
-                                                     Reduce *R) {
+                                                     const T *__restrict__ q, State *st,
+                                                     Reduce *R, const DD *pq, int32_t pq_count) {
   using P2 = typename Pair<T>::type;
   if (st->flag != kRunning) return;
+  T alpha;
+  if (pq) {
+    __shared__ double s_alpha;
+    __shared__ int s_ok;
+    const double rho = st->rho;
+    const DD *src[1] = {pq};
+    finish_in_block<1>(src, pq_count, [&](DD (&v)[1]) {
+      const double pqv = dd_round(v[0]);
+      const bool ok = pqv != 0.0 && finite(pqv);
+      s_ok = ok;
+      s_alpha = ok ? rho / pqv : 0.0;
+      if (blockIdx.x == 0) {
+        if (ok)
+          st->alpha = s_alpha;
+        else
+          st->flag = kBreakdown;
+      }
+    });
+    __syncthreads();
+    if (!s_ok) return;  // block-uniform
+    alpha = T(s_alpha);
+  } else {
+    alpha = T(st->alpha);
+  }
   const bool first = st->k == 0;
   const bool defer = (st->k & 1) == 0;  // x waits for the next iteration
-  const T beta = T(st->beta), alpha = T(st->alpha), alpha_x = T(st->alpha_x);
+  const T beta = T(st->beta), alpha_x = T(st->alpha_x);
   Dot2 a;
   // rows i and i + kBlock of each tile of 2 kBlock rows, the loads of both in
   // flight together (a row past n re-reads row n - 1 and stores nothing)
