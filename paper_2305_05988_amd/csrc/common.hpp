@@ -297,10 +297,6 @@ __global__ void __launch_bounds__(kBlock) k_finish_final(Reduce *R, int count, i
   finish_in_block<ND>(src, count, fin);
 }
 
-// Partials that a consuming pass may reduce in each of its blocks instead of
-// a finishing kernel (the second-level count of the largest grids is 256).
-constexpr int kFusedFinish = 512;
-
 // Blocks of the first finishing level (0 when one kernel finishes).
 inline int finish_grid(int G) { return G <= kFinishOne ? 0 : (G + kGroup - 1) / kGroup; }
 

@@ -613,8 +613,10 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
       const int GA = op.grid();
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, (k_cg_pass1<decltype(op), double>), GA, op, (const double2_t *)rp, q, (const State *)w.st, w.R);
-        // p.q: the update pass reduces a few hundred partials itself; more
-        // first-level partials are first summed per group of kGroup
+        // p.q: with two reduction levels the update pass sums the group sums
+        // (at most kGroup) itself instead of a finishing kernel.  It never
+        // reads first-level partials: its own blocks overwrite those with
+        // their r.r partials while others may still be starting.
         const DD *pq = nullptr;
         int32_t pqn = 0;
         if (GA > kFinishOne) {
@@ -622,9 +624,6 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
           LAUNCH(run, kClassFinish, k_finish_group<1>, nb, w.R, GA);
           pq = reinterpret_cast<const DD *>(reinterpret_cast<const char *>(w.R) + offsetof(Reduce, p2));
           pqn = nb;
-        } else if (GA <= kFusedFinish) {
-          pq = reinterpret_cast<const DD *>(reinterpret_cast<const char *>(w.R) + offsetof(Reduce, p1));
-          pqn = GA;
         } else {
           FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
         }

@@ -116,11 +116,12 @@ struct FinCg1 {
   }
 };
 
-// pq, pq_count: when pq is not null, the SpMV pass's p.q partials (first- or
-// second-level, a few hundred at most), which every block reduces itself in
-// the finishing kernel's order (finish_in_block) and turns into alpha as
-// FinCg1 does -- block 0 records alpha, or the breakdown, in the State -- so
-// no finishing kernel runs between the two passes.
+// pq, pq_count: when pq is not null, the SpMV pass's p.q as second-level
+// (group) sums, at most kGroup, which every block reduces itself in the
+// finishing kernel's order (finish_in_block) and turns into alpha as FinCg1
+// does -- block 0 records alpha, or the breakdown, in the State -- so no
+// finishing kernel runs between the two passes.  They must not be
+// first-level partials: this pass writes its own partials there.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x,
                                                      typename Pair<T>::type *__restrict__ rp,
