@@ -161,7 +161,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
   // flight together (a row past n re-reads row n - 1 and stores nothing)
   const int64_t ntiles = (int64_t(n) + 2 * kBlock - 1) / (2 * kBlock);
   const Sched sc = my_tiles(ntiles);
-  for (int64_t t = sc.begin; t < sc.end; t += sc.stride) {
+  // the tiles are walked from the end of each XCD's chunk, where the SpMV
+  // pass that ran just before finished, so the start of this pass finds
+  // some of the lines that pass touched last still in the memory-side cache
+  // (the partial slots and the rows of each block are those of a forward
+  // walk; only the order in which a block's Dot2 takes its tiles differs)
+  const int64_t last = sc.begin < sc.end ? sc.begin + (sc.end - 1 - sc.begin) / sc.stride * sc.stride
+                                         : sc.begin - sc.stride;
+  for (int64_t t = last; t >= sc.begin; t -= sc.stride) {
     int32_t i[2];
     i[0] = int32_t(t * 2 * kBlock + threadIdx.x);
     i[1] = i[0] + kBlock;

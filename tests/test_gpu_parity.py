@@ -513,6 +513,23 @@ def test_sgs_two_colours_tiny(pack, n):
         assert info.iters == rr.iters and np.array_equal(host(x), ref), (rtol, cap)
 
 
+@pytest.mark.parametrize("g", [(1, 1, 1), (2, 1, 1), (3, 1, 1), (1, 1, 2), (2, 2, 1), (3, 3, 3),
+                               (13, 9, 7)])
+def test_sgs_two_colours_stencil_edges(g):
+    """The 7-point matrix-free half-sweeps on their compact colour index:
+    grids with one cell, an empty black colour, odd sides (lines whose red
+    cells start at x = 1), at a fixed count and converged."""
+    Acsr = inputs.poisson7_csr(*g)
+    S = its().StencilMatrix(*g, inputs.POISSON7)
+    col = inputs.redblack_colors(*g)
+    b = inputs.uniform_vector(S.n, 5)
+    for rtol, cap in ((0.0, 3), (1e-12, 400)):
+        ref, rr = oracle.sgs(Acsr, col, 2, b, rtol=rtol, max_iter=cap)
+        x, info = its().solve(S, dev(b), method="sgs", rtol=rtol, max_iter=cap)
+        assert info.iters == rr.iters and np.array_equal(host(x), ref), (rtol, cap)
+        assert abs(info.rel_res - rr.rel_res) <= 1e-12 * rr.rel_res
+
+
 def test_sgs_rejects_bad_colouring():
     g = (6, 6, 6)
     Acsr, A = _matrix("csr27", g)
