@@ -39,11 +39,9 @@ struct its_matrix {
   int32_t *color_rows = nullptr;
   std::vector<int32_t> color_off;
   int diag_state = 0;  // CSR: 0 unchecked, 1 every row has a nonzero diagonal, -1 not
-  State *host_state = nullptr;  // pinned snapshot buffer for polling (two States,
+  State *host_state = nullptr;  // pinned snapshot buffer for polling (two States and
                                 // one more block for words read back after a
-                                // persistent kernel, and the second buffer of
-                                // the overlapped polls)
-  hipEvent_t poll_ev[2] = {nullptr, nullptr};  // completion of the overlapped polls
+                                // persistent kernel)
   // Packed copy (its_csr_pack), owned: sliced ELLPACK of col/val and of the
   // low-precision values that were set when it was packed.
   int64_t *sp = nullptr;
@@ -178,22 +176,16 @@ struct Prof {
     used += 2;
     open = false;
   }
-  size_t mark() const { return cls.size(); }
-  // Adds up the first `upto` timed launches (all of them by default), whose
-  // events have completed: after a stream synchronisation, or after waiting
-  // for work enqueued after them.  The pending ones move to the front.
-  void flush(size_t upto = SIZE_MAX) {
-    upto = std::min(upto, cls.size());
-    for (size_t p = 0; p < upto; ++p) {
+  void flush() {  // after a stream synchronisation
+    for (size_t p = 0; p < cls.size(); ++p) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]) == hipSuccess) {
         res->kernel_ms[cls[p]] += ms;
         res->kernel_launches[cls[p]] += 1;
       }
     }
-    std::rotate(ev.begin(), ev.begin() + 2 * upto, ev.begin() + used);
-    cls.erase(cls.begin(), cls.begin() + upto);
-    used -= 2 * upto;
+    cls.clear();
+    used = 0;
   }
 };
 
@@ -201,8 +193,6 @@ struct Run {
   hipStream_t s;
   Prof prof;
   its_matrix::GraphCache *gc = nullptr;  // null: launch each iteration eagerly
-  State *poll2 = nullptr;                 // second pinned snapshot (overlapped polls)
-  hipEvent_t pev[2] = {nullptr, nullptr};
   std::vector<uint64_t> key;             // what the captured launches depend on
   template <class K, class... Args>
   hipError_t launch(int cls, K kernel, int grid, Args... args) {
@@ -465,57 +455,10 @@ its_status iterate_graph(Run &run, const State *dev, State *host, int64_t max_it
   }
 }
 
-// Steps in batches of m with a poll of the device State after each.  With
-// the two poll events the next batch is enqueued before the host waits for
-// the previous batch's snapshot, so the GPU does not idle while the host
-// reads it and launches again; the steps after a stop are no-ops on the
-// device (every pass and finishing kernel checks the State's flag), as are
-// the rest of a batch within which the solve stops.  At most max_iter steps
-// are enqueued either way.
 template <class Step>
 its_status iterate(Run &run, const State *dev, State *host, int64_t max_iter, int m, Step &&step,
                    bool eager_first = false) {
   if (run.gc && run.prof.every == 0) return iterate_graph(run, dev, host, max_iter, m, eager_first, step);
-  if (run.poll2 && run.poll2 != host && run.pev[0] && run.pev[1]) {
-    State *buf[2] = {host, run.poll2};
-    bool inflight[2] = {false, false};
-    size_t marks[2] = {0, 0};
-    int64_t j = 0;
-    auto issue = [&](int slot) -> its_status {
-      const int64_t todo = std::min<int64_t>(m, max_iter - j);
-      for (int64_t t = 0; t < todo; ++t, ++j) {
-        its_status st = step(j);
-        if (st != ITS_OK) return st;
-      }
-      HIP_TRY(hipMemcpyAsync(buf[slot], dev, sizeof(State), hipMemcpyDeviceToHost, run.s));
-      HIP_TRY(hipEventRecord(run.pev[slot], run.s));
-      inflight[slot] = true;
-      marks[slot] = run.prof.mark();
-      return ITS_OK;
-    };
-    its_status st = issue(0);
-    if (st != ITS_OK) return st;
-    if (j < max_iter && (st = issue(1)) != ITS_OK) return st;
-    // slot cur holds the older of the batches in flight
-    for (int cur = 0;; cur ^= 1) {
-      HIP_TRY(hipEventSynchronize(run.pev[cur]));
-      inflight[cur] = false;
-      run.prof.flush(marks[cur]);
-      marks[cur ^ 1] -= std::min(marks[cur ^ 1], marks[cur]);
-      if (buf[cur]->flag != kRunning) {
-        HIP_TRY(hipStreamSynchronize(run.s));  // the no-op batch behind it
-        run.prof.flush();
-        if (cur != 0) *host = *buf[cur];
-        return ITS_OK;
-      }
-      if (j < max_iter && (st = issue(cur)) != ITS_OK) return st;
-      if (!inflight[cur ^ 1]) {
-        // no older batch left in flight: the one just issued is next, if any
-        if (!inflight[cur]) return fail(ITS_E_HIP, "device state still running after max_iter");
-        cur ^= 1;
-      }
-    }
-  }
   int64_t j = 0;
   for (;;) {
     const int64_t todo = std::min<int64_t>(m, max_iter - j);
@@ -1159,15 +1102,12 @@ static its_status new_matrix(its_matrix **out) {
   its_matrix *A = new (std::nothrow) its_matrix();
   if (!A) return fail(ITS_E_INVALID, "out of host memory");
   void *p = nullptr;
-  if (hipHostMalloc(&p, 4 * sizeof(State), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&p, 3 * sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete A;
     return fail(ITS_E_HIP, "hipHostMalloc of the state snapshot failed");
   }
   A->host_state = static_cast<State *>(p);
-  std::memset(A->host_state, 0, 4 * sizeof(State));
-  // without the two events the iteration loops poll without overlap
-  for (auto &e : A->poll_ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  std::memset(A->host_state, 0, 3 * sizeof(State));
   *out = A;
   return ITS_OK;
 }
@@ -1269,8 +1209,6 @@ its_status its_matrix_destroy(its_matrix *A) {
   if (A->own_val) (void)hipFree(A->own_val);
   if (A->color_rows) (void)hipFree(A->color_rows);
   if (A->host_state) (void)hipHostFree(A->host_state);
-  for (auto e : A->poll_ev)
-    if (e) (void)hipEventDestroy(e);
   free_packed(A);
   drop_graph(A);
   if (A->graph.ev) (void)hipEventDestroy(A->graph.ev);
@@ -1873,11 +1811,6 @@ static its_status solve_impl(const its_matrix *Ac, const its_options *o, const d
   // the key lists what the captured launches depend on
   its_matrix *owner = const_cast<its_matrix *>(Ac);
   run.gc = (o->graph == 1 && cache_graph) ? &owner->graph : nullptr;
-  if (owner->poll_ev[0] && owner->poll_ev[1]) {
-    run.poll2 = owner->host_state + 3;
-    run.pev[0] = owner->poll_ev[0];
-    run.pev[1] = owner->poll_ev[1];
-  }
   if (run.gc) {
     uint64_t rt;
     std::memcpy(&rt, &o->restart_tol, sizeof(rt));
