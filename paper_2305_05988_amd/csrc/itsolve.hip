@@ -627,7 +627,7 @@ its_status solve_cg(Run &run, const its_matrix *A, const its_options *o, const d
         } else {
           FINISH(run, 1, w.R, GA, (FinCg1{w.st}));
         }
-        LAUNCH(run, 1, k_cg_pass2<double>, G2, n, x, rp, (const double *)q, w.st, w.R, pq, pqn);
+        LAUNCH(run, 1, (k_cg_pass2<double, GathersPairs<decltype(op)>::value>), G2, n, x, rp, (const double *)q, w.st, w.R, pq, pqn);
         FINISH(run, 1, w.R, G2, (FinCg2{w.st}));
         return ITS_OK;
       });
@@ -680,7 +680,7 @@ its_status solve_cgnb(Run &run, const its_matrix *A, const its_options *o, const
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, k_cgnb_x<decltype(op)>, GA, op, (const double2_t *)ra, wv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinCgnbX{w.st}));
-        LAUNCH(run, 1, k_cgnb_y, G, n, x, ra, p, (const double *)wv, (const State *)w.st, w.R);
+        LAUNCH(run, 1, k_cgnb_y<GathersPairs<decltype(op)>::value>, G, n, x, ra, p, (const double *)wv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, G, (FinCgnbY{w.st}));
         return ITS_OK;
       });
@@ -769,13 +769,13 @@ its_status solve_ir(Run &run, const its_matrix *A, const its_options *o, const d
             if (pairs) {
               LAUNCH(run, 0, (k_cg_pass1_pairs<decltype(op)>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
               FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
-              LAUNCH(run, 1, k_cg_pass2_f32x2, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
+              LAUNCH(run, 1, k_cg_pass2_f32x2<GathersPairs<decltype(op)>::value>, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
               FINISH(run, 1, w.R, G2, (FinCg2{w.st2}));
               return ITS_OK;
             }
           LAUNCH(run, 0, (k_cg_pass1<decltype(op), float>), GA, op, (const float2_t *)rhp, q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, GA, (FinCg1{w.st2}));
-          LAUNCH(run, 1, k_cg_pass2_f32x2, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
+          LAUNCH(run, 1, k_cg_pass2_f32x2<GathersPairs<decltype(op)>::value>, G2, n, d, rhp, (const float *)q, (const State *)w.st2, w.R);
           FINISH(run, 1, w.R, G2, (FinCg2{w.st2}));
           return ITS_OK;
         });
@@ -843,7 +843,7 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
         FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
         LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double2_t *)rv, t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
-        LAUNCH(run, 2, k_bicg_c, GC, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
+        LAUNCH(run, 2, k_bicg_c<GathersPairs<decltype(op)>::value>, GC, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GC, (FinBicgC{w.st, rt2, paper}));
         return ITS_OK;
       });

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double2_t *__rest
       double2_t o;
       o.x = ri;
       o.y = acc;
-      st_nt(rv + i, o);
+      st_pairs<GathersPairs<Op>::value>(rv + i, o);
       double rsi;
       if (restart) {
         rsi = ri / rn;
@@ -145,6 +145,7 @@ struct FinBicgB {
   }
 };
 
+template <bool Keep>
 __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict__ x,
                                                    double2_t *__restrict__ ru,
                                                    const double *__restrict__ rs,
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_c(int32_t n, double *__restrict
       double2_t o;
       o.x = ri;
       o.y = fma(-om, e[h].y, pi[h]);  // u = p - omega v
-      st_nt(ru + i[h], o);
+      st_pairs<Keep>(ru + i[h], o);
       a0.add(ri, rsi[h]);
       a1.add(ri, ri);
     }

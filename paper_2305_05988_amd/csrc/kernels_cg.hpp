@@ -122,7 +122,7 @@ struct FinCg1 {
 // does -- block 0 records alpha, or the breakdown, in the State -- so no
 // finishing kernel runs between the two passes.  They must not be
 // first-level partials: this pass writes its own partials there.
-template <class T>
+template <class T, bool Keep>
 __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ x,
                                                      typename Pair<T>::type *__restrict__ rp,
                                                      const T *__restrict__ q, State *st,
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2(int32_t n, T *__restrict__ 
       P2 o;
       o.x = ri;
       o.y = pi;
-      st_nt(rp + i[h], o);
+      st_pairs<Keep>(rp + i[h], o);
       a.add(double(ri), double(ri));
     }
   }
@@ -226,6 +226,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_flush_x32(int32_t n, float *__res
 // would halve that and leave the pass instruction-bound).  Row arithmetic is
 // that of k_cg_pass2<float>; the dot partial is exact before its final
 // rounding, so the pairing of rows does not change it.
+template <bool Keep>
 __global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__restrict__ x,
                                                            float2_t *__restrict__ rp,
                                                            const float *__restrict__ q,
@@ -263,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass2_f32x2(int32_t n, float *__r
     o.z = o1.x;
     o.w = o1.y;
     if (!defer) st_nt(reinterpret_cast<float2_t *>(x) + i, xo);
-    st_nt(reinterpret_cast<float4_t *>(rp) + i, o);
+    st_pairs<Keep>(reinterpret_cast<float4_t *>(rp) + i, o);
   });
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // the last row of an odd n
     const int32_t i = n - 1;

@@ -100,6 +100,7 @@ struct FinCgnbX {
   }
 };
 
+template <bool Keep>
 __global__ void __launch_bounds__(kBlock) k_cgnb_y(int32_t n, double *__restrict__ x,
                                                    double2_t *__restrict__ ra,
                                                    double *__restrict__ p,
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_y(int32_t n, double *__restrict
     double2_t o;
     o.x = ri;
     o.y = api;
-    st_nt(ra + i, o);
+    st_pairs<Keep>(ra + i, o);
     a.add(api, pi);
   });
   DD v[1] = {a.get()};

@@ -16,6 +16,10 @@ namespace its {
 // LDS hold x_j (the pass's value of what it loads for row j), and each row
 // reads its neighbours from them.  Rows keep the CSR chain order.
 template <int NPTS, class T>
+struct StencilOp;
+template <int NPTS, class T> struct GathersPairs<StencilOp<NPTS, T>> : std::false_type {};
+
+template <int NPTS, class T>
 struct StencilOp {
   int32_t nx, ny, nz, n;
   T c[NPTS];

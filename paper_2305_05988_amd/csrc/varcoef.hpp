@@ -18,6 +18,9 @@ namespace its {
 // in ascending column order, so the operator equals the CSR matrix built
 // with the same roundings bit for bit.  A is symmetric (each face value is
 // formed once, from its lower cell), so it is its own transpose.
+struct VarCoefOp;
+template <> struct GathersPairs<VarCoefOp> : std::false_type {};
+
 struct VarCoefOp {
   int32_t nx, ny, nz, n;
   const double *__restrict__ k;
