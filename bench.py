@@ -581,7 +581,7 @@ def kernel_suite(its, inputs, iters=10):
         run(A, b, method="cg", rtol=1e-12, max_iter=iters, inner_dtype=lowp, inner_rtol=1e-30)
     out["poisson256_packed"] = {
         "n": n, "grid_spmv": (n + 255) // 256,
-        "k_cg_pass1<SellOp<double": M + 3 * V, "k_cg_pass2<double": 6 * V,
+        "k_cg_pass1<SellOp<double": M + 3 * V, "k_cg_pass2<double, true": 6 * V,
         "k_jacobi<SellOp<double": M + 3 * V,
         "k_cg_pass1<SellOp<float": M32 + 3 * V32, "k_cg_pass1_pairs<SellOp<__half": M16 + 3 * V32,
         "k_cg_pass2_f32x2": 6 * V32, "k_residual<SellOp<double": M + 3 * V}
@@ -625,7 +625,7 @@ def kernel_suite(its, inputs, iters=10):
     V3, V3_32 = 8 * n2, 4 * n2
     out["stencil27_192_packed"] = {
         "n": n2, "k_cg_pass1<SellOp<double": packed_matrix_bytes(A3, n2) + 3 * V3,
-        "k_cg_pass2<double": 6 * V3,
+        "k_cg_pass2<double, true": 6 * V3,
         "k_cg_pass1_pairs<SellOp<float": packed_lowp_bytes(A3, n2, 4) + 3 * V3_32,
         "k_cg_pass1_pairs<SellOp<__half": packed_lowp_bytes(A3, n2, 2) + 3 * V3_32,
         "k_cg_pass2_f32x2": 6 * V3_32}
