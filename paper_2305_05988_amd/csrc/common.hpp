@@ -151,9 +151,22 @@ struct Sched {
   int64_t begin, end, stride;
 };
 
-__device__ __forceinline__ Sched my_tiles(int64_t ntiles) {
+// The block's place in that schedule.  A pass that runs backwards (rev)
+// gives block b the place mirrored among its XCD's blocks, so the blocks
+// dispatched first take the ends of the chunks and the pass ends at their
+// starts, where the next pass begins; its block partials are stored at the
+// place, so the reduction, and every bit of the result, is the forward
+// pass's.
+__device__ __forceinline__ int sched_place(bool rev) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (!rev) return b;
+  if (G < 64 || (G % kXcds) != 0) return G - 1 - b;
+  return (G / kXcds - 1 - b / kXcds) * kXcds + b % kXcds;
+}
+
+__device__ __forceinline__ Sched my_tiles(int64_t ntiles, bool rev = false) {
   const int G = gridDim.x;
-  const int b = blockIdx.x;
+  const int b = sched_place(rev);
   if (G < 64 || (G % kXcds) != 0) return {b, ntiles, G};
   const int x = b % kXcds, slot = b / kXcds, per = G / kXcds;
   const int64_t lo = ntiles * x / kXcds, hi = ntiles * (x + 1) / kXcds;
@@ -162,9 +175,9 @@ __device__ __forceinline__ Sched my_tiles(int64_t ntiles) {
 
 // Element-wise walk: body(i) for the thread's row of each of its tiles.
 template <class Body>
-__device__ __forceinline__ void for_rows(int32_t n, Body &&body) {
+__device__ __forceinline__ void for_rows(int32_t n, Body &&body, bool rev = false) {
   const int64_t ntiles = (int64_t(n) + kBlock - 1) / kBlock;
-  const Sched s = my_tiles(ntiles);
+  const Sched s = my_tiles(ntiles, rev);
   for (int64_t t = s.begin; t < s.end; t += s.stride) {
     const int64_t i = t * kBlock + threadIdx.x;
     if (i < n) body(int32_t(i));
@@ -174,9 +187,9 @@ __device__ __forceinline__ void for_rows(int32_t n, Body &&body) {
 // Tile walk: body(r0, r1) for each of the block's tiles, called by every
 // thread of the block (the body may synchronise the block).
 template <class Body>
-__device__ __forceinline__ void for_tiles(int32_t n, Body &&body) {
+__device__ __forceinline__ void for_tiles(int32_t n, Body &&body, bool rev = false) {
   const int64_t ntiles = (int64_t(n) + kBlock - 1) / kBlock;
-  const Sched s = my_tiles(ntiles);
+  const Sched s = my_tiles(ntiles, rev);
   for (int64_t t = s.begin; t < s.end; t += s.stride) {
     const int32_t r0 = int32_t(t * kBlock);
     const int32_t r1 = int32_t(min(int64_t(n), t * kBlock + kBlock));
@@ -245,11 +258,12 @@ struct Reduce {
 // No fence and no atomic: the finishing kernels, launched after this one on
 // the same stream, see the stores at the kernel boundary.
 template <int ND>
-__device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R) {
+__device__ __forceinline__ void block_partial(DD (&v)[ND], Reduce *R, bool rev = false) {
   block_reduce<ND>(v);
   if (threadIdx.x == 0) {
+    const int at = sched_place(rev);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) R->p1[d][blockIdx.x] = v[d];
+    for (int d = 0; d < ND; ++d) R->p1[d][at] = v[d];
   }
 }
 

@@ -10,6 +10,7 @@
 #include <limits>
 #include <mutex>
 #include <type_traits>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -308,6 +309,20 @@ WS carve(void *ws, const Layout &L, int64_t) {
 }
 
 // ------------------------------------------------------------ operators
+
+// A CSR operator's launch that sweeps its tiles backwards (Backwards); the
+// matrix-free operators are launched as they are.
+#define LAUNCH_OP(run, cls, K, rev, grid, op, ...)                                              \
+  do {                                                                                        \
+    using Op_ = decltype(op);                                                                 \
+    if constexpr (GathersPairs<Op_>::value) {                                                 \
+      if (rev) {                                                                              \
+        LAUNCH(run, cls, K<Backwards<Op_>>, grid, Backwards<Op_>{op}, __VA_ARGS__);           \
+        break;                                                                                \
+      }                                                                                       \
+    }                                                                                         \
+    LAUNCH(run, cls, K<Op_>, grid, op, __VA_ARGS__);                                          \
+  } while (0)
 
 template <class F>
 its_status with_op64(const its_matrix *A, F &&f) {
@@ -841,7 +856,8 @@ its_status solve_bicgstab(Run &run, const its_matrix *A, const its_options *o, c
       return iterate(run, w.st, h, o->max_iter, batch_size(o, n), [&](int64_t) -> its_status {
         LAUNCH(run, 0, k_bicg_a<decltype(op)>, GA, op, (const double2_t *)ru, rs, p, rv, (const State *)w.st, w.R);
         FINISH(run, 1, w.R, GA, (FinBicgA{w.st}));
-        LAUNCH(run, 1, k_bicg_b<decltype(op)>, GA, op, (const double2_t *)rv, t, (const State *)w.st, w.R);
+        // backwards: it starts on the {r, v} pairs pass A wrote last
+        LAUNCH_OP(run, 1, k_bicg_b, true, GA, op, (const double2_t *)rv, t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GA, (FinBicgB{w.st}));
         LAUNCH(run, 2, k_bicg_c<GathersPairs<decltype(op)>::value>, GC, n, x, ru, (const double *)rs, (const double *)p, (const double2_t *)rv, (const double *)t, (const State *)w.st, w.R);
         FINISH(run, 2, w.R, GC, (FinBicgC{w.st, rt2, paper}));
@@ -891,7 +907,8 @@ its_status solve_jacobi(Run &run, its_matrix *A, const its_options *o, const dou
     const int GA = op.grid();
     return iterate(run, w.st, h, steps_for(o->max_iter), batch_size(o, n), [&](int64_t j) -> its_status {
       const int a = int(j & 1);
-      LAUNCH(run, 0, k_jacobi<decltype(op)>, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
+      // odd sweeps run backwards: each starts on the x values the previous one wrote last
+      LAUNCH_OP(run, 0, k_jacobi, a == 1, GA, op, b, (const double *)X[a], X[a ^ 1], (const State *)w.st, w.R);
       FINISH(run, 1, w.R, GA, (FinJacobi{w.st}));
       return ITS_OK;
     });

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(Op A, const double *__restr
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill(int32_t n, double *x, double v) {

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_a(Op A, const double2_t *__rest
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 // alpha_d = v.r', alpha = alpha_n / alpha_d; the restart (if any) is consumed.
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_b(Op A, const double2_t *__rest
     }
   });
   DD d[2] = {a0.get(), a1.get()};
-  block_partial<2>(d, R);
+  block_partial<2>(d, R, rev_of(A));
 }
 
 // omega = (t.s) / (t.t), 0 if t.t = 0.

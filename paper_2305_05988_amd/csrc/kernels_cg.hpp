@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pass1(Op A,
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 // Pass 1 of the refinement's FP32 inner CG on an FP32/FP16 offset-slice

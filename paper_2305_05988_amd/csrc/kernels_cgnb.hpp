@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_init(Op A, double2_t *__restric
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 struct FinCgnbInit {  // alpha_d,0 and alpha_0
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_x(Op A, const double2_t *__rest
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 // alpha_n,j; beta and gamma for pass Y.
@@ -124,9 +124,9 @@ __global__ void __launch_bounds__(kBlock) k_cgnb_y(int32_t n, double *__restrict
     o.y = api;
     st_pairs<Keep>(ra + i, o);
     a.add(api, pi);
-  });
+  }, Keep);  // backwards with kept pairs: k_cgnb_x starts where this ends
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, Keep);
 }
 
 // alpha_d,j; one more iteration; the test on alpha_n,j (the residual of the

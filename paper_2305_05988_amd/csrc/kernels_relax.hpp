@@ -34,11 +34,11 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const double *__restric
       const double bi = ld_nt(b + i);
       const double ri = bi - full;
       a.add(ri, ri);
-      st_nt(xn + i, (bi - off) / diag);
+      st_pairs<GathersPairs<Op>::value>(xn + i, (bi - off) / diag);
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 // The sweep's residual belongs to x_k: test it; if it fails, x_{k+1} is the
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_check(Op A, const double *__restr
     }
   });
   DD v[1] = {a.get()};
-  block_partial<1>(v, R);
+  block_partial<1>(v, R, rev_of(A));
 }
 
 // Residual of x_{k+1} after a symmetric iteration, and the test.

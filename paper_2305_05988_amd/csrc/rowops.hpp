@@ -34,6 +34,22 @@ namespace its {
 
 constexpr int kGather = 8;
 
+// An operator whose 1-D tile sweep (tiled_rows, tiled_own_rows) runs
+// backwards (sched_place); only for the CSR operators, whose rows() is the
+// tile sweep.  The direction is part of the type, so a forward kernel pays
+// nothing for it.
+template <class Op>
+struct Backwards;
+
+template <class Op>
+__host__ __device__ constexpr bool rev_of(const Op &) {
+  return false;
+}
+template <class Op>
+__host__ __device__ constexpr bool rev_of(const Backwards<Op> &) {
+  return true;
+}
+
 // rows() for the operators that walk 1-D tiles of kBlock rows.
 template <class Op, class Load, class Value, class Body>
 __device__ __forceinline__ void tiled_rows(const Op &A, typename Op::Smem &sm, Load &&load,
@@ -47,7 +63,7 @@ __device__ __forceinline__ void tiled_rows(const Op &A, typename Op::Smem &sm, L
     };
     auto own = [&]() { return value(load(i)); };
     body(i, i < r1, entries, own);
-  });
+  }, rev_of(A));
 }
 
 // The rows a thread owns in tiled_rows(), in the same order: body(i).  A
@@ -55,8 +71,21 @@ __device__ __forceinline__ void tiled_rows(const Op &A, typename Op::Smem &sm, L
 // this thread handled there.
 template <class Op, class Body>
 __device__ __forceinline__ void tiled_own_rows(const Op &A, Body &&body) {
-  for_rows(A.n, body);
+  for_rows(A.n, body, rev_of(A));
 }
+
+template <class Op>
+struct Backwards : Op {
+  template <class Load, class Value, class Body>
+  __device__ __forceinline__ void rows(typename Op::Smem &sm, Load &&load, Value &&value,
+                                       Body &&body) const {
+    tiled_rows(*this, sm, load, value, body);
+  }
+  template <class Body>
+  __device__ __forceinline__ void own_rows(Body &&body) const {
+    tiled_own_rows(*this, body);
+  }
+};
 
 __device__ __forceinline__ double widen(double v) { return v; }
 __device__ __forceinline__ float widen(float v) { return v; }
