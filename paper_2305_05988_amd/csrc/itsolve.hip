@@ -968,10 +968,17 @@ its_status solve_sgs(Run &run, its_matrix *A, const its_options *o, const double
       if (!A->cpack.empty()) {
         const auto &cp = A->cpack[size_t(c)];
         const int32_t *rows = A->color_rows + beg;
-        if (!cp.col)  // every slice an offset slice
-          LAUNCH(run, 0, (k_gs_rows_packed<M, SellOp<double, double, true>>), Gc, SellOp<double, double, true>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, rows}, rows, b, x, xs, (const State *)w.st, w.R);
-        else
+        if (!cp.col) {  // every slice an offset slice
+          // with two colours the red half-sweeps run backwards: each starts on the rows
+          // the black one before it wrote last
+          const SellOp<double, double, true> op{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, rows};
+          if (nc == 2 && c == 0)
+            LAUNCH(run, 0, (k_gs_rows_packed<M, Backwards<SellOp<double, double, true>>>), Gc, Backwards<SellOp<double, double, true>>{op}, rows, b, x, xs, (const State *)w.st, w.R);
+          else
+            LAUNCH(run, 0, (k_gs_rows_packed<M, SellOp<double, double, true>>), Gc, op, rows, b, x, xs, (const State *)w.st, w.R);
+        } else {
           LAUNCH(run, 0, (k_gs_rows_packed<M, SellOp<double, double>>), Gc, SellOp<double, double>{cp.sp, cp.col, cp.val, cnt, cp.soff, cp.smask, rows}, rows, b, x, xs, (const State *)w.st, w.R);
+        }
         return ITS_OK;
       }
       LAUNCH(run, 0, k_gs_rows_csr<M>, Gc, CsrOp<double, double>{A->rp, A->col, A->val, n}, (const int32_t *)(A->color_rows + beg), cnt, b, x, xs, (const State *)w.st, w.R);

@@ -83,10 +83,10 @@ enum : int32_t { kGsPlain = 0, kGsFinal = 1, kGsLagged = 2 };
 
 // One dot's block partial into slot d; the other slots are left alone (the
 // red and black residual partials of one test come from two kernels).
-__device__ __forceinline__ void block_partial_at(DD v, int d, Reduce *R) {
+__device__ __forceinline__ void block_partial_at(DD v, int d, Reduce *R, bool rev = false) {
   DD t[1] = {v};
   block_reduce<1>(t);
-  if (threadIdx.x == 0) R->p1[d][blockIdx.x] = t[0];
+  if (threadIdx.x == 0) R->p1[d][sched_place(rev)] = t[0];
 }
 
 template <int Mode>
@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(kBlock) k_gs_rows_packed(Op A, const int32_t *
         a.add(ri, ri);
       }
     }
-  });
-  if (Mode != kGsPlain) block_partial_at(a.get(), Mode == kGsFinal ? 0 : 1, R);
+  }, rev_of(A));
+  if (Mode != kGsPlain) block_partial_at(a.get(), Mode == kGsFinal ? 0 : 1, R, rev_of(A));
 }
 
 // Matrix-free half-sweep over one colour's cells, walked on a compact index
